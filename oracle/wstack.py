@@ -1,0 +1,230 @@
+"""Reference w-stacking imager in float64 (the oracle's O-WS part).
+
+Test infrastructure only: the imaging library never imports, links or calls this.
+
+It follows the method of Sec. 2 of the paper in its own order:
+  1. baselines in wavelengths, (u, v, w) = uvw * nu / c  (Eq. 1 defines u, v, w in wavelengths);
+     grid positions x = u / du + N/2, y = v / du + N/2 with du = 1 / (N * dl);
+  2. the W taps start at floor(x + 1/2) - (W-1)/2; a visibility whose taps leave
+     the grid, or whose uvw or weight is not finite, is dropped;
+  3. Nw uniform w-planes over [w_lo, w_hi] (Eq. 2's integration range), each
+     visibility going to the plane that holds it (the "closest w-plane" of Sec. 2):
+     k = clamp(floor((w - w_lo) / dw), 0, Nw-1), plane centre w_k = w_lo + (k + 1/2) dw;
+  4. the separable Kaiser-Bessel kernel G (oracle.kb);
+  5. convolutional gridding, Eq. 3: grid_k[p0+b][q0+a] += W_m V_m G(q0+a-x) G(p0+b-y);
+  6. each plane's 2D transform with the + sign of Eq. 2 and the phase centre at N/2:
+     P_k(i,j) = sum_{p,q} grid_k[p][q] exp(+2 pi i [(q-N/2)(j-N/2) + (p-N/2)(i-N/2)] / N);
+  7. the w-correction and reduction of the planes ("phase shift and reduction of
+     w-planes", Sec. 2; the w-term sign of Eq. 2):
+     S(i,j) = sum_k P_k(i,j) exp(+2 pi i w_k (n_ij - 1));
+  8. division by the kernel's Fourier transform on both axes and by the sum of
+     weights (natural weighting, Sec. 4.2.1): D = Re S / (sum W * C(xi_j) C(xi_i)),
+     xi_j = (j - N/2) / N.
+
+Pixel (i, j): row i carries m_i = (i - N/2) dl, column j carries l_j = (j - N/2) dl.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import kb as _kb
+from ._native import lib as _lib, ptr as _ptr
+
+C_LIGHT = 299_792_458.0
+
+
+@dataclasses.dataclass
+class Params:
+    n: int
+    pixel_rad: float
+    n_wplanes: int
+    support: int
+    beta: float
+    w_lo: Optional[float] = None    # both None: the range comes from the data
+    w_hi: Optional[float] = None
+
+
+@dataclasses.dataclass
+class Prepared:
+    """Steps 1-3 for every input row (arrays are full length M)."""
+    u: np.ndarray
+    v: np.ndarray
+    w: np.ndarray
+    x: np.ndarray
+    y: np.ndarray
+    q0: np.ndarray      # int64, first tap column (meaningful where keep)
+    p0: np.ndarray      # int64, first tap row
+    keep: np.ndarray    # bool
+    k: np.ndarray       # int64 plane index (meaningful where keep)
+    w_lo: float
+    w_hi: float
+    dw: float
+    sum_w: float
+
+    @property
+    def n_kept(self) -> int:
+        return int(self.keep.sum())
+
+
+def prepare(uvw_m: np.ndarray, weights: np.ndarray, freq_hz: float, prm: Params) -> Prepared:
+    """Steps 1-3: wavelength coordinates, tap origins, the keep mask and plane indices."""
+    uvw_m = np.asarray(uvw_m, dtype=np.float64)
+    wt = np.asarray(weights).astype(np.float64)
+    n, W = prm.n, prm.support
+    u = uvw_m[:, 0] * freq_hz / C_LIGHT
+    v = uvw_m[:, 1] * freq_hz / C_LIGHT
+    w = uvw_m[:, 2] * freq_hz / C_LIGHT
+    du = 1.0 / (n * prm.pixel_rad)
+    x = u / du + n / 2
+    y = v / du + n / 2
+    half = (W - 1) // 2
+    with np.errstate(invalid="ignore"):
+        fq = np.floor(x + 0.5) - half
+        fp = np.floor(y + 0.5) - half
+        finite = np.isfinite(uvw_m).all(axis=1) & np.isfinite(wt)
+        keep = finite & (fq >= 0) & (fq + W - 1 <= n - 1) & (fp >= 0) & (fp + W - 1 <= n - 1)
+    q0 = np.where(keep, fq, 0).astype(np.int64)
+    p0 = np.where(keep, fp, 0).astype(np.int64)
+
+    if prm.w_lo is not None and prm.w_hi is not None:
+        w_lo, w_hi = float(prm.w_lo), float(prm.w_hi)
+    else:
+        sel = keep & (wt > 0)
+        if sel.any():
+            w_lo, w_hi = float(w[sel].min()), float(w[sel].max())
+        else:
+            w_lo = w_hi = 0.0
+    dw = (w_hi - w_lo) / prm.n_wplanes
+    if dw == 0.0:
+        k = np.zeros(u.shape[0], dtype=np.int64)
+    else:
+        with np.errstate(invalid="ignore"):
+            kf = np.floor((w - w_lo) / dw)
+        kf = np.where(keep, kf, 0)
+        k = np.clip(kf, 0, prm.n_wplanes - 1).astype(np.int64)
+    sum_w = float(wt[keep].sum())
+    return Prepared(u, v, w, x, y, q0, p0, keep, k, w_lo, w_hi, dw, sum_w)
+
+
+def tap_weights(pr: Prepared, prm: Params, rows: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Step 4 at the taps of the given rows: gx[r, a] = G(q0+a-x), gy[r, b] = G(p0+b-y)."""
+    a = np.arange(prm.support)
+    gx = _kb.kb((pr.q0[rows, None] + a[None, :]) - pr.x[rows, None], prm.support, prm.beta)
+    gy = _kb.kb((pr.p0[rows, None] + a[None, :]) - pr.y[rows, None], prm.support, prm.beta)
+    return np.ascontiguousarray(gx), np.ascontiguousarray(gy)
+
+
+def grid_plane(pr: Prepared, vis: np.ndarray, weights: np.ndarray, prm: Params, plane: int,
+               chunk: int = 1 << 20) -> np.ndarray:
+    """Step 5 for one w-plane: the complex float64 grid [N, N] of Eq. 3."""
+    n = prm.n
+    grid = np.zeros((n, n, 2), dtype=np.float64)
+    rows = np.nonzero(pr.keep & (pr.k == plane))[0]
+    vis = np.asarray(vis)
+    wt = np.asarray(weights).astype(np.float64)
+    L = _lib()
+    for c0 in range(0, rows.size, chunk):
+        r = rows[c0:c0 + chunk]
+        wv = wt[r] * vis[r].astype(np.complex128)
+        wv_re = np.ascontiguousarray(wv.real)
+        wv_im = np.ascontiguousarray(wv.imag)
+        gx, gy = tap_weights(pr, prm, r)
+        idx = np.arange(r.size, dtype=np.int64)
+        p0 = np.ascontiguousarray(pr.p0[r])
+        q0 = np.ascontiguousarray(pr.q0[r])
+        L.oracle_grid_accumulate(n, prm.support, r.size, _ptr(idx), _ptr(p0), _ptr(q0),
+                                 _ptr(wv_re), _ptr(wv_im), _ptr(gx), _ptr(gy), _ptr(grid))
+    return grid[..., 0] + 1j * grid[..., 1]
+
+
+def _centred_phase(idx_a: np.ndarray, idx_b: np.ndarray, n: int) -> np.ndarray:
+    """exp(+2 pi i (a - N/2)(b - N/2) / N) for all pairs, with the product reduced mod N exactly."""
+    a = (np.asarray(idx_a, dtype=np.int64) - n // 2)[:, None]
+    b = (np.asarray(idx_b, dtype=np.int64) - n // 2)[None, :]
+    r = np.mod(a * b, n)
+    return np.exp(2j * math.pi * (r / n))
+
+
+def plane_transform(grid: np.ndarray, pixels: Optional[Tuple[Sequence[int], Sequence[int]]] = None
+                    ) -> np.ndarray:
+    """Step 6.  Full plane: N^2 * fftshift(ifft2(ifftshift(grid))) (numpy's ifft has the + sign).
+
+    With pixels = (rows I, cols J) the same sum is taken directly at the product set I x J
+    as two matrix products over the non-zero grid rows.
+    """
+    n = grid.shape[0]
+    if pixels is None:
+        return (n * n) * np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(grid)))
+    rows_i, cols_j = (np.asarray(pixels[0]), np.asarray(pixels[1]))
+    nz = np.nonzero(np.any(grid != 0, axis=1))[0]
+    if nz.size == 0:
+        return np.zeros((rows_i.size, cols_j.size), dtype=np.complex128)
+    ecol = _centred_phase(np.arange(n), cols_j, n)          # [q, j]
+    erow = _centred_phase(nz, rows_i, n)                     # [p, i]
+    t = grid[nz] @ ecol                                      # [p, j]
+    return erow.T @ t                                        # [i, j]
+
+
+def direction_cosines(n: int, pixel_rad: float, rows, cols):
+    """l_j, m_i and n_ij - 1 for the product set rows x cols (float64).
+
+    n - 1 is evaluated as -(l^2 + m^2) / (1 + sqrt(1 - l^2 - m^2)), which equals
+    sqrt(1 - l^2 - m^2) - 1 without its cancellation.
+    """
+    lj = (np.asarray(cols, dtype=np.float64) - n // 2) * pixel_rad
+    mi = (np.asarray(rows, dtype=np.float64) - n // 2) * pixel_rad
+    r2 = mi[:, None] ** 2 + lj[None, :] ** 2
+    if np.any(r2 >= 1.0):
+        raise ValueError("pixel beyond the horizon (l^2 + m^2 >= 1)")
+    nm1 = -r2 / (1.0 + np.sqrt(1.0 - r2))
+    return lj, mi, nm1
+
+
+def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
+                 pixels: Optional[Tuple[Sequence[int], Sequence[int]]] = None,
+                 planes: Optional[Sequence[int]] = None, complex_out: bool = False,
+                 prepared: Optional[Prepared] = None) -> np.ndarray:
+    """Steps 1-8: the dirty image [N, N] (or [|I|, |J|] at pixels = (I, J)).
+
+    ``planes`` restricts steps 5-7 to a subset of w-planes (the rest contribute
+    nothing); the normalisation keeps the full sum of weights.
+    """
+    n = prm.n
+    pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
+    if pixels is None:
+        rows = cols = np.arange(n)
+    else:
+        rows, cols = np.asarray(pixels[0]), np.asarray(pixels[1])
+    shape = (rows.size, cols.size)
+    if pr.sum_w == 0.0:
+        return np.zeros(shape, dtype=np.complex128 if complex_out else np.float64)
+    _, _, nm1 = direction_cosines(n, prm.pixel_rad, rows, cols)
+    S = np.zeros(shape, dtype=np.complex128)
+    plist = range(prm.n_wplanes) if planes is None else planes
+    for k in plist:
+        if not np.any(pr.keep & (pr.k == k)):
+            continue
+        g = grid_plane(pr, vis, weights, prm, k)
+        P = plane_transform(g, None if pixels is None else (rows, cols))
+        del g
+        wk = pr.w_lo + (k + 0.5) * pr.dw
+        cyc = wk * nm1
+        cyc = cyc - np.round(cyc)
+        S += P * np.exp(2j * math.pi * cyc)
+    xi_j = (cols - n // 2) / n
+    xi_i = (rows - n // 2) / n
+    corr = np.outer(_kb.kb_taper(xi_i, prm.support, prm.beta), _kb.kb_taper(xi_j, prm.support, prm.beta))
+    D = S / (pr.sum_w * corr)
+    return D if complex_out else D.real
+
+
+def grid_stack(uvw_m, vis, weights, freq_hz: float, prm: Params,
+               prepared: Optional[Prepared] = None) -> np.ndarray:
+    """Step 5 for every plane: the complex float64 grid [Nw, N, N]."""
+    pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
+    return np.stack([grid_plane(pr, vis, weights, prm, k) for k in range(prm.n_wplanes)])
