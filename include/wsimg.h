@@ -1,0 +1,169 @@
+/*
+ * wsimg.h -- C ABI of the w-stacking dirty imager for AMD MI355X (gfx950).
+ *
+ * The library turns visibilities into a dirty image with the w-stacking method
+ * of Sec. 2 of the paper: visibilities are sorted into grid strips, convolved
+ * onto the nearest of Nw w-planes with a separable Kaiser-Bessel kernel (Eq. 3),
+ * each plane is 2D Fourier transformed, multiplied by its w-term phase and the
+ * planes are summed (Eq. 2, "phase shift and reduction of w-planes"), and the
+ * result is divided by the kernel's Fourier transform and by the sum of weights.
+ *
+ * Conventions (every entry point):
+ *  - All calls return a wsimg_status; 0 is success, negative values are errors.
+ *    No C++ exception crosses this boundary.  wsimg_last_error() returns a
+ *    thread-local text describing the most recent error of the calling thread.
+ *  - Array arguments marked "device" are device pointers on the GPU the plan was
+ *    created on; the caller owns them and they must stay valid until the work
+ *    enqueued on the plan's stream has completed.  The plan owns its scratch.
+ *  - Work is enqueued on the plan's HIP stream and returns without waiting,
+ *    except where a stats pointer is given (then the call waits for the stream).
+ *  - Counts are int64_t (the paper's I/O section notes the 32-bit count limit of
+ *    the MPI read calls; no count here is 32-bit).
+ *  - A plan is not thread-safe; separate plans are independent.
+ *
+ * Geometry (Sec. 2, Eq. 1): u, v, w are the baseline coordinates in wavelengths,
+ * (u, v, w) = uvw_m * freq_hz / c with c = 299792458 m/s.  The image is n x n,
+ * row-major; pixel (i, j) has direction cosines l = (j - n/2) * pixel_rad and
+ * m = (i - n/2) * pixel_rad.  The grid is n x n cells of size 1/(n * pixel_rad)
+ * wavelengths, with no padding (the paper sizes its grid as the image: an
+ * 8192^2 grid of 32 w-planes is 32 GB, Sec. 4.2.1).
+ */
+#ifndef WSIMG_H
+#define WSIMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WSIMG_OK = 0,
+    WSIMG_E_INVALID = -1,      /* an argument is out of range or a pointer is NULL        */
+    WSIMG_E_NOMEM = -2,        /* device or host allocation failed                        */
+    WSIMG_E_HIP = -3,          /* a HIP runtime call or a kernel launch failed            */
+    WSIMG_E_EMPTY = -4,        /* the kept visibilities have zero total weight           */
+    WSIMG_E_CAPACITY = -5,     /* n_vis exceeds the plan's max_vis                        */
+    WSIMG_E_UNSUPPORTED = -6   /* valid parameters this build does not implement          */
+} wsimg_status;
+
+typedef enum {
+    WSIMG_F32 = 1,   /* vis complex64, weights float32, grid/FFT/stacking float32 (Kahan
+                        sum over planes); coordinates and the w-phase argument in float64 */
+    WSIMG_F64 = 2    /* vis complex128, weights float64, everything float64              */
+} wsimg_precision;
+
+/* wsimg_params.flags */
+#define WSIMG_FIXED_WRANGE 0x1u   /* use w_lo/w_hi below instead of the data's range     */
+
+typedef struct {
+    int32_t n;          /* image side = grid side: a power of two, 16..8192 (16384 is
+                           accepted as valid and reported WSIMG_E_UNSUPPORTED)           */
+    int32_t n_wplanes;  /* Nw >= 1, <= 4096                                                */
+    int32_t support;    /* Kaiser-Bessel support W in cells: odd, 3..15                    */
+    int32_t precision;  /* wsimg_precision                                                 */
+    double pixel_rad;   /* pixel size dl > 0; every pixel must satisfy l^2 + m^2 < 1      */
+    double beta;        /* Kaiser-Bessel shape; <= 0 selects 2.34 * support                */
+    double w_lo, w_hi;  /* plane range in wavelengths when WSIMG_FIXED_WRANGE is set       */
+    uint32_t flags;
+    uint32_t reserved;  /* must be 0 */
+} wsimg_params;
+
+typedef struct {
+    int64_t n_in;       /* rows passed in                                                  */
+    int64_t n_gridded;  /* rows kept: finite uvw and weight, all W x W taps on the grid    */
+    int64_t n_dropped;  /* n_in - n_gridded                                                */
+    double sum_w;       /* sum of the kept weights (the image is divided by it)           */
+    double w_lo, w_hi;  /* plane range used                                                */
+} wsimg_stats;
+
+typedef struct {
+    int32_t n, n_wplanes, support, precision;
+    int32_t strip_rows;      /* grid rows per gridding work-group                          */
+    int32_t col_block;       /* image columns per stacking work-group                      */
+    int64_t n_buckets;       /* sort buckets: n_wplanes * n / strip_rows                   */
+    int64_t max_vis;
+    int64_t device_bytes;    /* device memory the plan holds                               */
+} wsimg_plan_info;
+
+#define WSIMG_N_KERNELS 7
+typedef struct {
+    int64_t calls;                     /* wsimg_image/wsimg_grid calls timed since enabling   */
+    double ms[WSIMG_N_KERNELS];        /* summed device time of each kernel stage             */
+    double ms_total;                   /* summed time from the first to the last stage         */
+} wsimg_timing;
+
+typedef struct wsimg_plan wsimg_plan;
+
+/*
+ * Create a plan for one imaging geometry on the current HIP device.
+ *  out       : receives the plan (set to NULL on error).
+ *  p         : parameters, copied; validated on the host before any HIP call.
+ *  max_vis   : largest n_vis a call may pass, 0 .. 4294967294; scratch is sized from it.
+ *  hip_stream: hipStream_t the plan's work is enqueued on (NULL = default stream).
+ * Errors: WSIMG_E_INVALID (parameters), WSIMG_E_UNSUPPORTED (n = 16384),
+ *         WSIMG_E_NOMEM (device memory), WSIMG_E_HIP.
+ */
+wsimg_status wsimg_plan_create(wsimg_plan **out, const wsimg_params *p, int64_t max_vis,
+                               void *hip_stream);
+
+/* Release a plan and its device memory (waits for its stream).  NULL is a no-op. */
+wsimg_status wsimg_plan_destroy(wsimg_plan *plan);
+
+/* Switch the stream later calls enqueue on. */
+wsimg_status wsimg_plan_set_stream(wsimg_plan *plan, void *hip_stream);
+
+/* Geometry and memory of a plan. */
+wsimg_status wsimg_plan_get_info(const wsimg_plan *plan, wsimg_plan_info *info);
+
+/*
+ * The dirty image (Sec. 2: Eqs. 1-3 and the phase shift and reduction of w-planes):
+ *   D(i,j) = Re sum_k P_k(i,j) exp(+2 pi i w_k (n_ij - 1)) / (sum W * C(xi_j) C(xi_i))
+ * where P_k is the 2D transform (exp(+2 pi i ...), phase centre at n/2) of plane k of the
+ * Kaiser-Bessel grid, w_k the plane centre, n_ij = sqrt(1 - l^2 - m^2) and C the kernel's
+ * Fourier transform at xi = (j - n/2)/n.
+ *  n_vis     : rows, 0 .. max_vis.
+ *  uvw_m     : device, [n_vis][3] float64 row-major, metres.
+ *  vis       : device, [n_vis] interleaved complex (float2 for F32, double2 for F64).
+ *  weights   : device, [n_vis] float (F32) / double (F64); natural weighting (Sec. 4.2.1).
+ *  freq_hz   : > 0, finite.
+ *  image_out : device, [n][n] float (F32) / double (F64), row-major; fully overwritten.
+ *  stats     : NULL, or receives the counters; non-NULL makes the call wait for the stream.
+ * Rows whose uvw or weight is not finite, or whose W x W taps leave the grid, are dropped
+ * and counted.  Planes span [w_lo, w_hi] of the kept rows with positive weight (or the
+ * fixed range); a row goes to plane clamp(floor((w - w_lo)/dw), 0, Nw-1).
+ * If the kept weights sum to zero the image is all zeros; with stats the call then
+ * returns WSIMG_E_EMPTY.
+ * Errors: WSIMG_E_INVALID, WSIMG_E_CAPACITY, WSIMG_E_HIP, WSIMG_E_EMPTY.
+ */
+wsimg_status wsimg_image(wsimg_plan *plan, int64_t n_vis, const double *uvw_m,
+                         const void *vis, const void *weights, double freq_hz,
+                         void *image_out, wsimg_stats *stats);
+
+/*
+ * The gridding step alone (Eq. 3 with the separable kernel, nearest w-plane):
+ *   grid_out[k][p][q] = sum over kept rows of plane k of W_m V_m G(q - x_m) G(p - y_m)
+ * where x = u / du + n/2, y = v / du + n/2 and du = 1/(n * pixel_rad).
+ *  grid_out : device, [n_wplanes][n][n] interleaved complex of the plan's precision;
+ *             fully overwritten.  Other arguments as wsimg_image.
+ * Errors: as wsimg_image.
+ */
+wsimg_status wsimg_grid(wsimg_plan *plan, int64_t n_vis, const double *uvw_m,
+                        const void *vis, const void *weights, double freq_hz,
+                        void *grid_out, wsimg_stats *stats);
+
+/* Per-stage device timing with HIP events on the plan's stream (enable != 0 turns it on and
+ * clears the totals).  wsimg_read_timing waits for the stream and returns the totals. */
+wsimg_status wsimg_set_timing(wsimg_plan *plan, int32_t enable);
+wsimg_status wsimg_read_timing(wsimg_plan *plan, wsimg_timing *out);
+const char *wsimg_stage_name(int32_t stage);   /* NULL when out of range */
+
+const char *wsimg_status_string(wsimg_status s);
+const char *wsimg_last_error(void);
+int32_t wsimg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSIMG_H */

@@ -150,18 +150,19 @@ def _centred_phase(idx_a: np.ndarray, idx_b: np.ndarray, n: int) -> np.ndarray:
     return np.exp(2j * math.pi * (r / n))
 
 
-def plane_transform(grid: np.ndarray, pixels: Optional[Tuple[Sequence[int], Sequence[int]]] = None
-                    ) -> np.ndarray:
+def plane_transform(grid: np.ndarray, pixels: Optional[Tuple[Sequence[int], Sequence[int]]] = None,
+                    grid_rows: Optional[np.ndarray] = None) -> np.ndarray:
     """Step 6.  Full plane: N^2 * fftshift(ifft2(ifftshift(grid))) (numpy's ifft has the + sign).
 
     With pixels = (rows I, cols J) the same sum is taken directly at the product set I x J
-    as two matrix products over the non-zero grid rows.
+    as two matrix products over the grid rows that can be non-zero (``grid_rows``, by
+    default every row holding a non-zero cell).
     """
     n = grid.shape[0]
     if pixels is None:
         return (n * n) * np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(grid)))
     rows_i, cols_j = (np.asarray(pixels[0]), np.asarray(pixels[1]))
-    nz = np.nonzero(np.any(grid != 0, axis=1))[0]
+    nz = np.nonzero(np.any(grid != 0, axis=1))[0] if grid_rows is None else np.asarray(grid_rows)
     if nz.size == 0:
         return np.zeros((rows_i.size, cols_j.size), dtype=np.complex128)
     ecol = _centred_phase(np.arange(n), cols_j, n)          # [q, j]
@@ -210,7 +211,12 @@ def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
         if not np.any(pr.keep & (pr.k == k)):
             continue
         g = grid_plane(pr, vis, weights, prm, k)
-        P = plane_transform(g, None if pixels is None else (rows, cols))
+        if pixels is None:
+            P = plane_transform(g)
+        else:
+            sel = pr.keep & (pr.k == k)
+            lo, hi = int(pr.p0[sel].min()), int(pr.p0[sel].max()) + prm.support - 1
+            P = plane_transform(g, (rows, cols), grid_rows=np.arange(lo, hi + 1))
         del g
         wk = pr.w_lo + (k + 0.5) * pr.dw
         cyc = wk * nm1

@@ -1,0 +1,191 @@
+"""w-stacking dirty imager for AMD MI355X (gfx950): Python binding of libwsimg.so.
+
+Every step of the imaging path runs in the HIP kernels behind the C ABI declared in
+include/wsimg.h; this module only checks tensor arguments, hands device pointers and the
+current HIP stream to the library, and turns status codes into exceptions.  PyTorch is
+used for device memory and streams.  There is no CPU fallback: if the library is not
+built, importing the binding's entry points raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+from . import _lib
+
+__all__ = ["WsimgError", "Plan", "image", "grid", "stage_names", "version"]
+
+
+class WsimgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"wsimg status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+def _check(status: int):
+    if status != _lib.WSIMG_OK:
+        L = _lib.load()
+        raise WsimgError(status, L.wsimg_last_error().decode() or L.wsimg_status_string(status).decode())
+
+
+def version() -> int:
+    return int(_lib.load().wsimg_version())
+
+
+def stage_names():
+    L = _lib.load()
+    return [L.wsimg_stage_name(i).decode() for i in range(_lib.WSIMG_N_KERNELS)]
+
+
+def _prec_code(precision: str) -> int:
+    if precision in ("f32", "float32"):
+        return _lib.WSIMG_F32
+    if precision in ("f64", "float64"):
+        return _lib.WSIMG_F64
+    raise ValueError(f"precision must be 'f32' or 'f64', got {precision!r}")
+
+
+class Plan:
+    """One imaging geometry on one GPU: owns the library plan and its device scratch."""
+
+    def __init__(self, n: int, pixel_rad: float, n_wplanes: int, support: int = 7,
+                 beta: Optional[float] = None, precision: str = "f32", max_vis: int = 0,
+                 w_range: Optional[Tuple[float, float]] = None, device=None):
+        import torch
+
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.precision = "f32" if _prec_code(precision) == _lib.WSIMG_F32 else "f64"
+        self.n, self.n_wplanes, self.support = int(n), int(n_wplanes), int(support)
+        p = _lib.Params()
+        p.n, p.n_wplanes, p.support = self.n, self.n_wplanes, self.support
+        p.precision = _prec_code(precision)
+        p.pixel_rad = float(pixel_rad)
+        p.beta = 0.0 if beta is None else float(beta)
+        p.flags = 0
+        if w_range is not None:
+            p.w_lo, p.w_hi = float(w_range[0]), float(w_range[1])
+            p.flags |= _lib.WSIMG_FIXED_WRANGE
+        self._L = _lib.load()
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _check(self._L.wsimg_plan_create(ctypes.byref(self._h), ctypes.byref(p), int(max_vis),
+                                             ctypes.c_void_p(stream)))
+        self.max_vis = int(max_vis)
+
+    # -- helpers -------------------------------------------------------------------------
+    def _dtypes(self):
+        t = self._torch
+        return (t.complex64, t.float32) if self.precision == "f32" else (t.complex128, t.float64)
+
+    def _args(self, uvw, vis, weights):
+        t = self._torch
+        cdt, rdt = self._dtypes()
+        m = int(uvw.shape[0]) if uvw.dim() == 2 else -1
+        if uvw.dtype != t.float64 or uvw.dim() != 2 or uvw.shape[1] != 3:
+            raise ValueError("uvw must be a float64 tensor of shape [M, 3] (metres)")
+        if vis.dtype != cdt or vis.shape != (m,):
+            raise ValueError(f"vis must be {cdt} of shape [M]")
+        if weights.dtype != rdt or weights.shape != (m,):
+            raise ValueError(f"weights must be {rdt} of shape [M]")
+        for name, x in (("uvw", uvw), ("vis", vis), ("weights", weights)):
+            if x.device != self.device:
+                raise ValueError(f"{name} must live on {self.device}")
+            if not x.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+        return m
+
+    def _stream(self):
+        s = self._torch.cuda.current_stream(self.device).cuda_stream
+        _check(self._L.wsimg_plan_set_stream(self._h, ctypes.c_void_p(s)))
+
+    def _run(self, fn, uvw, vis, weights, freq_hz, out, stats):
+        m = self._args(uvw, vis, weights)
+        self._stream()
+        st = _lib.Stats()
+        status = fn(self._h, m, ctypes.c_void_p(uvw.data_ptr()), ctypes.c_void_p(vis.data_ptr()),
+                    ctypes.c_void_p(weights.data_ptr()), float(freq_hz), ctypes.c_void_p(out.data_ptr()),
+                    ctypes.byref(st) if stats else None)
+        _check(status)
+        if stats:
+            return out, {f: getattr(st, f) for f, _ in _lib.Stats._fields_}
+        return out
+
+    # -- the calls -------------------------------------------------------------------------
+    def image(self, uvw, vis, weights, freq_hz: float, out=None, stats: bool = False):
+        """Dirty image [n, n] (wsimg_image).  With stats=True returns (image, stats dict)."""
+        _, rdt = self._dtypes()
+        if out is None:
+            out = self._torch.empty((self.n, self.n), dtype=rdt, device=self.device)
+        elif out.dtype != rdt or out.shape != (self.n, self.n) or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous [n, n] tensor of the plan's real dtype on its device")
+        return self._run(self._L.wsimg_image, uvw, vis, weights, freq_hz, out, stats)
+
+    def grid(self, uvw, vis, weights, freq_hz: float, out=None, stats: bool = False):
+        """The gridding step alone: complex grid [n_wplanes, n, n] (wsimg_grid)."""
+        cdt, _ = self._dtypes()
+        shape = (self.n_wplanes, self.n, self.n)
+        if out is None:
+            out = self._torch.empty(shape, dtype=cdt, device=self.device)
+        elif out.dtype != cdt or tuple(out.shape) != shape or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous [n_wplanes, n, n] tensor of the plan's complex dtype")
+        return self._run(self._L.wsimg_grid, uvw, vis, weights, freq_hz, out, stats)
+
+    def info(self) -> dict:
+        i = _lib.PlanInfo()
+        _check(self._L.wsimg_plan_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _lib.PlanInfo._fields_}
+
+    def set_timing(self, enable: bool = True):
+        _check(self._L.wsimg_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        t = _lib.Timing()
+        _check(self._L.wsimg_read_timing(self._h, ctypes.byref(t)))
+        names = stage_names()
+        return {"calls": t.calls, "ms_total": t.ms_total, "ms": {names[i]: t.ms[i] for i in range(len(names))}}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.wsimg_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def image(uvw, vis, weights, freq_hz: float, *, n: int, pixel_rad: float, n_wplanes: int,
+          support: int = 7, beta: Optional[float] = None, precision: Optional[str] = None,
+          w_range=None, stats: bool = False):
+    """One-shot dirty image (creates and frees a plan)."""
+    import torch
+    if precision is None:
+        precision = "f64" if vis.dtype == torch.complex128 else "f32"
+    with Plan(n, pixel_rad, n_wplanes, support, beta, precision, max_vis=uvw.shape[0],
+              w_range=w_range, device=uvw.device) as p:
+        return p.image(uvw, vis, weights, freq_hz, stats=stats)
+
+
+def grid(uvw, vis, weights, freq_hz: float, *, n: int, pixel_rad: float, n_wplanes: int,
+         support: int = 7, beta: Optional[float] = None, precision: Optional[str] = None,
+         w_range=None, stats: bool = False):
+    """One-shot gridding step (creates and frees a plan)."""
+    import torch
+    if precision is None:
+        precision = "f64" if vis.dtype == torch.complex128 else "f32"
+    with Plan(n, pixel_rad, n_wplanes, support, beta, precision, max_vis=uvw.shape[0],
+              w_range=w_range, device=uvw.device) as p:
+        return p.grid(uvw, vis, weights, freq_hz, stats=stats)

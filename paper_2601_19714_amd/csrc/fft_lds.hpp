@@ -1,0 +1,205 @@
+// Batched 1D complex FFTs of compile-time length held in LDS, for a whole work-group.
+//
+// Transform (the sign of Eq. 2, unnormalised):  X[j] = sum_q x[q] exp(+2 pi i q j / N),
+// N = 2^LOG2N, applied to ROWS rows stored back to back (row r at element r*N, every
+// element index passed through lds_pad).  Stockham autosort: each pass reads R inputs
+// a stride N/R apart, twiddles them, runs an R-point DFT in registers and writes the R
+// outputs a stride L apart, so the result ends in natural order with no bit reversal.
+// Pass layout: radix 16 first, then one radix-2/4/8 pass when LOG2N is not a multiple of
+// 4, then radix 16.  Twiddles come from a table tw[t] = exp(+2 pi i t / N) built in
+// float64 on the host.  Every pass is written for NT threads with NT * 16 >= ROWS * N.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace wsimg {
+
+template <typename C> __device__ __forceinline__ void dft2(C& a, C& b) {
+    C t = a; a = cadd(t, b); b = csub(t, b);
+}
+
+template <typename C> __device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+    C t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = cmuli(csub(a1, a3));
+    a0 = cadd(t0, t2); a2 = csub(t0, t2); a1 = cadd(t1, t3); a3 = csub(t1, t3);
+}
+
+// a * exp(+2 pi i e / 16) for the exponents a 4 x 4 split needs
+template <typename C> __device__ __forceinline__ C tw16(C a, int e) {
+    using R = decltype(C::x);
+    const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173, r2 = (R)0.70710678118654752440;
+    switch (e) {
+        case 0: return a;
+        case 1: return cmul(a, cmake<C>(c1, s1));
+        case 2: return cmake<C>(r2 * (a.x - a.y), r2 * (a.x + a.y));
+        case 3: return cmul(a, cmake<C>(s1, c1));
+        case 4: return cmuli(a);
+        case 6: return cmake<C>(-r2 * (a.x + a.y), r2 * (a.x - a.y));
+        case 9: return cmul(a, cmake<C>(-c1, -s1));
+        default: return a;
+    }
+}
+
+template <typename C> __device__ __forceinline__ void dft8(C* x) {
+    // n = 2 n1 + n2, m = m1 + 4 m2
+    dft4(x[0], x[2], x[4], x[6]);
+    dft4(x[1], x[3], x[5], x[7]);
+    x[3] = tw16(x[3], 2);     // m1 = 1: exp(2 pi i / 8)
+    x[5] = tw16(x[5], 4);     // m1 = 2
+    x[7] = tw16(x[7], 6);     // m1 = 3
+    dft2(x[0], x[1]); dft2(x[2], x[3]); dft2(x[4], x[5]); dft2(x[6], x[7]);
+    C y[8];
+#pragma unroll
+    for (int m1 = 0; m1 < 4; ++m1) { y[m1] = x[2 * m1]; y[m1 + 4] = x[2 * m1 + 1]; }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = y[i];
+}
+
+template <typename C> __device__ __forceinline__ void dft16(C* x) {
+    // n = 4 n1 + n2, m = m1 + 4 m2
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(x[n2], x[n2 + 4], x[n2 + 8], x[n2 + 12]);
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int m1 = 1; m1 < 4; ++m1) x[n2 + 4 * m1] = tw16(x[n2 + 4 * m1], n2 * m1);
+#pragma unroll
+    for (int m1 = 0; m1 < 4; ++m1) dft4(x[4 * m1], x[4 * m1 + 1], x[4 * m1 + 2], x[4 * m1 + 3]);
+    C y[16];
+#pragma unroll
+    for (int m1 = 0; m1 < 4; ++m1)
+#pragma unroll
+        for (int m2 = 0; m2 < 4; ++m2) y[m1 + 4 * m2] = x[4 * m1 + m2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = y[i];
+}
+
+template <int RAD, typename C> __device__ __forceinline__ void dft_small(C* x) {
+    if constexpr (RAD == 2) dft2(x[0], x[1]);
+    else if constexpr (RAD == 4) dft4(x[0], x[1], x[2], x[3]);
+    else if constexpr (RAD == 8) dft8(x);
+    else dft16(x);
+}
+
+template <int V> struct Log2Of {
+    static constexpr int value = V == 2 ? 1 : V == 4 ? 2 : V == 8 ? 3 : 4;          // radices
+    static constexpr int value_any = V <= 1 ? 0 : 1 + Log2Of<(V > 1 ? V / 2 : 1)>::value_any;
+};
+template <> struct Log2Of<1> { static constexpr int value = 0; static constexpr int value_any = 0; };
+
+// Pass layout of an N = 2^LOG2N transform (LOG2N >= 4).
+template <int LOG2N> struct FftPlan {
+    static constexpr int REM = LOG2N & 3;
+    // radix (log2) of the last pass; the only pass when LOG2N == 4
+    static constexpr int LAST_LOG = LOG2N <= 4 ? LOG2N : ((LOG2N < 8 && REM) ? REM : 4);
+    // log2 L at which the last pass starts
+    static constexpr int LAST_L = LOG2N - LAST_LOG;
+};
+
+// One Stockham pass (LDS to LDS) at sub-length L = 2^LOG2L.
+template <int RAD, int LOG2N, int LOG2L, int ROWS, int NT, typename C>
+__device__ __forceinline__ void stockham_pass(C* lds, const C* __restrict__ tw) {
+    constexpr int LOGR = Log2Of<RAD>::value;
+    constexpr int LSUB = LOG2N - LOGR;                     // log2(N / RAD)
+    constexpr int NBF = ROWS << LSUB;
+    constexpr int BPT = (NBF + NT - 1) / NT;               // butterflies per thread
+    constexpr int L = 1 << LOG2L;
+    constexpr int TWSHIFT = LOG2N - LOG2L - LOGR;
+    const int tid = threadIdx.x;
+    C x[BPT][RAD];
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+        const int g = tid + t * NT;
+        if (NBF % NT == 0 || g < NBF) {
+            const int r = g >> LSUB, b = g & ((1 << LSUB) - 1);
+            const int base = (r << LOG2N) + b;
+#pragma unroll
+            for (int m = 0; m < RAD; ++m) x[t][m] = lds[lds_pad(base + (m << LSUB))];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+        const int g = tid + t * NT;
+        if (NBF % NT == 0 || g < NBF) {
+            const int r = g >> LSUB, b = g & ((1 << LSUB) - 1);
+            const int k = b & (L - 1), j = b >> LOG2L;
+            if constexpr (L > 1) {
+#pragma unroll
+                for (int m = 1; m < RAD; ++m) x[t][m] = cmul(x[t][m], tw[(m * k) << TWSHIFT]);
+            }
+            dft_small<RAD>(x[t]);
+            const int obase = (r << LOG2N) + (j << (LOG2L + LOGR)) + k;
+#pragma unroll
+            for (int m = 0; m < RAD; ++m) lds[lds_pad(obase + (m << LOG2L))] = x[t][m];
+        }
+    }
+    __syncthreads();
+}
+
+// Passes from sub-length 2^LOG2L up to (not including) 2^STOP, in the plan's layout:
+// the radix-2/4/8 pass (if any) sits at LOG2L == 4, right after the first radix-16 pass.
+template <int LOG2N, int LOG2L, int STOP, int ROWS, int NT, typename C>
+__device__ __forceinline__ void stockham_range(C* lds, const C* __restrict__ tw) {
+    if constexpr (LOG2L < STOP) {
+        constexpr int REM = LOG2N & 3;
+        constexpr int LOGR = (REM != 0 && LOG2L == 4) ? REM : 4;
+        stockham_pass<(1 << LOGR), LOG2N, LOG2L, ROWS, NT>(lds, tw);
+        stockham_range<LOG2N, LOG2L + LOGR, STOP, ROWS, NT>(lds, tw);
+    }
+}
+
+// Full in-place transform of ROWS rows held in LDS (LOG2N >= 4).
+template <int LOG2N, int ROWS, int NT, typename C>
+__device__ __forceinline__ void fft_rows_lds(C* lds, const C* __restrict__ tw) {
+    static_assert(LOG2N >= 4, "transforms start with a radix-16 pass");
+    stockham_pass<16, LOG2N, 0, ROWS, NT>(lds, tw);
+    stockham_range<LOG2N, 4, LOG2N, ROWS, NT>(lds, tw);
+}
+
+// Last pass (L * RAD == N) from LDS into registers.  out[t * RAD + m] holds output bin
+// b + m * (N / RAD) of row (g >> LSUB), g = threadIdx.x + t * NT, b = g mod (N / RAD);
+// slots of inactive threads are zero.  No barrier at the end.
+template <int LOG2N, int ROWS, int NT, typename C>
+__device__ __forceinline__ void fft_last_to_regs(const C* lds, const C* __restrict__ tw, C* out) {
+    constexpr int LOGR = FftPlan<LOG2N>::LAST_LOG;
+    constexpr int RAD = 1 << LOGR;
+    constexpr int LSUB = LOG2N - LOGR;
+    constexpr int NBF = ROWS << LSUB;
+    constexpr int BPT = 16 / RAD;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+        const int g = tid + t * NT;
+        C x[RAD];
+        if (g < NBF) {
+            const int r = g >> LSUB, b = g & ((1 << LSUB) - 1);
+            const int base = (r << LOG2N) + b;
+#pragma unroll
+            for (int m = 0; m < RAD; ++m) x[m] = lds[lds_pad(base + (m << LSUB))];
+#pragma unroll
+            for (int m = 1; m < RAD; ++m) x[m] = cmul(x[m], tw[m * b]);
+            dft_small<RAD>(x);
+        } else {
+#pragma unroll
+            for (int m = 0; m < RAD; ++m) x[m] = cmake<C>(0, 0);
+        }
+#pragma unroll
+        for (int m = 0; m < RAD; ++m) out[t * RAD + m] = x[m];
+    }
+}
+
+// Row (column of the image block) c and bin i' held by register slot s (0..15) of thread
+// tid after fft_last_to_regs.
+template <int LOG2N, int ROWS, int NT>
+__device__ __forceinline__ bool last_slot(int tid, int s, int& c, int& ip) {
+    constexpr int LOGR = FftPlan<LOG2N>::LAST_LOG;
+    constexpr int LSUB = LOG2N - LOGR;
+    const int t = s >> LOGR, m = s & ((1 << LOGR) - 1);
+    const int g = tid + t * NT;
+    if (g >= (ROWS << LSUB)) return false;
+    c = g >> LSUB;
+    ip = (g & ((1 << LSUB) - 1)) + (m << LSUB);
+    return true;
+}
+
+}  // namespace wsimg

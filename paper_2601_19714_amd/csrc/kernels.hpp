@@ -1,0 +1,494 @@
+// The imaging kernels for gfx950.
+//
+//  k_fill_u32     : zero the bucket counters (a kernel, not a memset, so the stages can be
+//                   captured into a graph).
+//  k_reduce       : per-block partial (min w, max w, sum of weights, count) over kept rows.
+//  k_finalize     : fixed-order reduction of the partials -> plane range and sum of weights.
+//  k_key          : per row, the bucket (w-plane, row strip of its first tap row) and its rank
+//                   inside the bucket (a counting-sort histogram, Sec. 3.2's bucket sort).
+//  k_scan         : exclusive scan of the bucket counts; strip and plane occupancy flags.
+//  k_scatter      : sorted records {tap origin, sub-cell offsets, W*V} (SoA).
+//  k_grid_rows    : one work-group per occupied (plane, strip): Kaiser-Bessel gridding of every
+//                   record whose taps reach the strip into an LDS strip (Eq. 3), then the
+//                   row FFT of the strip in LDS; writes the strip in column-block layout.
+//                   The FFT-less variant writes the raw grid (the gridding step alone).
+//  k_cols_stack   : one work-group per block of image columns: for each plane, column FFTs
+//                   in LDS, multiply by the plane's w-phase, Kahan-accumulate the real part;
+//                   finally divide by the taper on both axes and the sum of weights.
+#pragma once
+
+#include "device_common.hpp"
+#include "fft_lds.hpp"
+
+namespace wsimg {
+
+// Plan constants handed to every kernel by value.
+struct Geom {
+    int n, log2n, nw, support, half;
+    int H, log2H, S;        // grid rows per strip, strips per plane
+    int B, log2B, NB;       // image columns per stacking block, blocks
+    int fixed_range;
+    double du, half_n, pixel;
+    double w_lo_fixed, w_hi_fixed;
+};
+
+// Written by k_finalize, read by the later stages.
+struct Scalars {
+    double w_lo, w_hi, dw, sum_w;
+    unsigned long long n_kept, n_in;
+};
+
+struct Partial {
+    double wmin, wmax, sumw;
+    unsigned long long nk;
+};
+
+template <typename R> struct KbDeg;
+template <> struct KbDeg<float> { static constexpr int value = 10; };
+template <> struct KbDeg<double> { static constexpr int value = 16; };
+
+// G(a - half - f) for f in [-1/2, 1/2]: a per-tap polynomial in f (coefficients fitted on the
+// host in extended precision at Chebyshev nodes), evaluated by Horner's rule.
+template <typename R>
+__device__ __forceinline__ R kb_tap(const R* __restrict__ coef, int a, R f) {
+    constexpr int D = KbDeg<R>::value;
+    const R* c = coef + a * (D + 1);
+    R acc = c[D];
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) acc = acc * f + c[d];
+    return acc;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_reduce_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_reduce_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block of 256 threads; block b covers rows [b*chunk, min(M, (b+1)*chunk)).
+template <typename WT>
+__global__ void __launch_bounds__(256)
+k_reduce(int64_t M, int64_t chunk, const double* __restrict__ uvw, const WT* __restrict__ wts,
+         double freq, Geom g, Partial* __restrict__ part) {
+    const int64_t beg = blockIdx.x * chunk;
+    const int64_t end = beg + chunk < M ? beg + chunk : M;
+    double wmin = INFINITY, wmax = -INFINITY, sw = 0.0;
+    unsigned long long nk = 0;
+    for (int64_t m = beg + threadIdx.x; m < end; m += blockDim.x) {
+        const double wt = (double)wts[m];
+        RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
+        if (rg.keep) {
+            sw += wt;
+            nk += 1;
+            if (wt > 0.0) { wmin = fmin(wmin, rg.w); wmax = fmax(wmax, rg.w); }
+        }
+    }
+    sw = wave_reduce_sum(sw);
+    nk = wave_reduce_sum(nk);
+    wmin = wave_reduce_min(wmin);
+    wmax = wave_reduce_max(wmax);
+    __shared__ Partial sh[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = Partial{wmin, wmax, sw, nk};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Partial t = sh[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            t.wmin = fmin(t.wmin, sh[i].wmin);
+            t.wmax = fmax(t.wmax, sh[i].wmax);
+            t.sumw += sh[i].sumw;
+            t.nk += sh[i].nk;
+        }
+        part[blockIdx.x] = t;
+    }
+}
+
+// One block of 256 threads; fixed summation order, so the sum of weights is reproducible.
+__global__ void __launch_bounds__(256)
+k_finalize(int nparts, const Partial* __restrict__ part, Geom g, int64_t M, Scalars* __restrict__ sc) {
+    __shared__ double s_sw[256], s_min[256], s_max[256];
+    __shared__ unsigned long long s_nk[256];
+    double sw = 0.0, mn = INFINITY, mx = -INFINITY;
+    unsigned long long nk = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        sw += part[i].sumw; nk += part[i].nk;
+        mn = fmin(mn, part[i].wmin); mx = fmax(mx, part[i].wmax);
+    }
+    s_sw[threadIdx.x] = sw; s_min[threadIdx.x] = mn; s_max[threadIdx.x] = mx; s_nk[threadIdx.x] = nk;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s_sw[threadIdx.x] += s_sw[threadIdx.x + o];
+            s_nk[threadIdx.x] += s_nk[threadIdx.x + o];
+            s_min[threadIdx.x] = fmin(s_min[threadIdx.x], s_min[threadIdx.x + o]);
+            s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma clang fp contract(off)
+        Scalars r;
+        if (g.fixed_range) { r.w_lo = g.w_lo_fixed; r.w_hi = g.w_hi_fixed; }
+        else if (s_min[0] <= s_max[0]) { r.w_lo = s_min[0]; r.w_hi = s_max[0]; }
+        else { r.w_lo = 0.0; r.w_hi = 0.0; }
+        r.dw = (r.w_hi - r.w_lo) / (double)g.nw;
+        r.sum_w = s_sw[0];
+        r.n_kept = s_nk[0];
+        r.n_in = (unsigned long long)M;
+        *sc = r;
+    }
+}
+
+template <typename WT>
+__global__ void __launch_bounds__(256)
+k_key(int64_t M, const double* __restrict__ uvw, const WT* __restrict__ wts, double freq, Geom g,
+      const Scalars* __restrict__ sc, uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
+      uint32_t* __restrict__ counts) {
+    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const double wt = (double)wts[m];
+    RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
+    uint32_t kk = 0xFFFFFFFFu, rr = 0;
+    if (rg.keep) {
+        const int k = plane_index(rg.w, sc->w_lo, sc->dw, g.nw);
+        const int p0 = (int)rg.cy - g.half;
+        kk = (uint32_t)(k * g.S + (p0 >> g.log2H));
+        rr = atomicAdd(&counts[kk], 1u);
+    }
+    key[m] = kk;
+    rank[m] = rr;
+}
+
+// One block of 1024 threads: exclusive scan of nb counts, then occupancy flags.
+// occ[k*S + s] = 1 when some record of plane k has a tap row inside strip s, i.e. one of the
+// buckets s_lo(s)..s (the strips whose rows can reach s) is non-empty.
+__global__ void __launch_bounds__(1024)
+k_scan(int nb, const uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, Geom g,
+       uint8_t* __restrict__ occ, uint8_t* __restrict__ plane_occ) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int chunk = (nb + nt - 1) / nt;
+    const int b0 = t * chunk;
+    const int b1 = b0 + chunk < nb ? b0 + chunk : nb;
+    uint32_t s = 0;
+    for (int b = b0; b < b1; ++b) s += counts[b];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {          // inclusive Hillis-Steele scan
+        uint32_t v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t > 0 ? part[t - 1] : 0u;
+    for (int b = b0; b < b1; ++b) { offsets[b] = run; run += counts[b]; }
+    if (t == nt - 1) offsets[nb] = part[nt - 1];
+    __syncthreads();
+    __threadfence_block();
+    for (int b = t; b < nb; b += nt) {
+        const int k = b / g.S, sidx = b - k * g.S;
+        int slo = ((sidx << g.log2H) - (g.support - 1)) >> g.log2H;
+        if (slo < 0) slo = 0;
+        occ[b] = offsets[k * g.S + sidx + 1] > offsets[k * g.S + slo] ? 1 : 0;
+    }
+    for (int k = t; k < g.nw; k += nt)
+        plane_occ[k] = offsets[(k + 1) * g.S] > offsets[k * g.S] ? 1 : 0;
+}
+
+template <typename R, typename WT>
+__global__ void __launch_bounds__(256)
+k_scatter(int64_t M, const double* __restrict__ uvw, const typename Cx<R>::T* __restrict__ vis,
+          const WT* __restrict__ wts, double freq, Geom g, const uint32_t* __restrict__ key,
+          const uint32_t* __restrict__ rank, const uint32_t* __restrict__ offsets,
+          uint32_t* __restrict__ rec_cell, typename Cx<R>::T* __restrict__ rec_frac,
+          typename Cx<R>::T* __restrict__ rec_vis) {
+    using C = typename Cx<R>::T;
+    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const uint32_t kk = key[m];
+    if (kk == 0xFFFFFFFFu) return;
+    const double wt = (double)wts[m];
+    RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
+    const uint32_t pos = offsets[kk] + rank[m];
+    const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
+    rec_cell[pos] = (uint32_t)q0 | ((uint32_t)p0 << 16);
+    rec_frac[pos] = cmake<C>((R)(rg.x - rg.cx), (R)(rg.y - rg.cy));
+    const C v = vis[m];
+    const R w = (R)wts[m];
+    rec_vis[pos] = cmake<C>(w * v.x, w * v.y);
+}
+
+// ---------------------------------------------------------------------------------------
+// Work-group shapes, fixed per (precision, image size).
+//   pass 1: H grid rows per strip, H * N <= 16384 (float) / 8192 (double) complex in LDS,
+//           NT1 = H * N / 16 threads (one radix-16 butterfly each per pass);
+//   pass 2: B image columns per block, B * N = 8192 (float) / 4096 (double) pixels,
+//           NT2 = B * N / 16 threads (16 output pixels each).
+template <typename R, int LOG2N> struct Shape {
+    static constexpr int N = 1 << LOG2N;
+    static constexpr int CAP1 = sizeof(R) == 4 ? 16384 : 8192;
+    static constexpr int H0 = CAP1 / N < 32 ? CAP1 / N : 32;
+    static constexpr int H = H0 < N / 2 ? H0 : N / 2;
+    static constexpr int NT1 = (H * N / 16) < 64 ? 64 : (H * N / 16);
+    static constexpr int PX2 = sizeof(R) == 4 ? 8192 : 4096;
+    static constexpr int B0 = PX2 / N < N ? PX2 / N : N;
+    static constexpr int B = B0 < 1 ? 1 : B0;
+    static constexpr int NT2 = (B * N / 16) < 64 ? 64 : (B * N / 16);
+    static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // complex elements
+    static constexpr int LDS2 = lds_padded_elems_c(B * N);                 // complex elements
+    // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer
+    static constexpr bool NM1_LDS =
+        (size_t)LDS2 * 2 * sizeof(R) + sizeof(double) * 16 * NT2 <= 160 * 1024;
+    static constexpr size_t LDS2_BYTES =
+        (size_t)LDS2 * 2 * sizeof(R) + (NM1_LDS ? sizeof(double) * 16 * NT2 : 0);
+};
+
+// ---------------------------------------------------------------------------------------
+// gridding (+ row FFT) of one (plane, strip) in LDS
+
+template <typename R, bool FFT, int LOG2N>
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
+k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restrict__ occ,
+            const uint32_t* __restrict__ rec_cell, const typename Cx<R>::T* __restrict__ rec_frac,
+            const typename Cx<R>::T* __restrict__ rec_vis, const R* __restrict__ kbc,
+            const typename Cx<R>::T* __restrict__ tw, typename Cx<R>::T* __restrict__ out) {
+    using C = typename Cx<R>::T;
+    using SH = Shape<R, LOG2N>;
+    constexpr int n = SH::N, H = SH::H, NT = SH::NT1, nmask = n - 1;
+    constexpr int LOG2H = Log2Of<H>::value_any;
+    constexpr int elems = H * n;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    const int nblk = g.nw * g.S;
+    const int logical = xcd_remap(blockIdx.x, nblk);
+    const int k = logical / g.S, s = logical - k * g.S;
+    const int tid = threadIdx.x;
+    const int row0 = s * H;
+    if (!occ[logical]) {
+        if constexpr (!FFT) {
+            C* dst = out + ((size_t)k << (2 * LOG2N)) + ((size_t)row0 << LOG2N);
+            for (int e = tid; e < elems; e += NT) dst[e] = cmake<C>((R)0, (R)0);
+        }
+        return;
+    }
+    for (int e = tid; e < SH::LDS1; e += NT) lds[e] = cmake<C>((R)0, (R)0);
+    __syncthreads();
+
+    const int W = g.support;
+    int s_lo = (row0 - (W - 1)) >> LOG2H;
+    if (s_lo < 0) s_lo = 0;
+    constexpr int shift = FFT ? (n >> 1) : 0;   // place cell q at (q + n/2) mod n: the centring
+    for (int sp = s_lo; sp <= s; ++sp) {
+        const uint32_t beg = offsets[k * g.S + sp], end = offsets[k * g.S + sp + 1];
+        for (uint32_t r = beg + tid; r < end; r += NT) {
+            const uint32_t cell = rec_cell[r];
+            const int q0 = (int)(cell & 0xFFFFu), p0 = (int)(cell >> 16);
+            int b_lo = row0 - p0;
+            if (b_lo < 0) b_lo = 0;
+            int b_hi = row0 + H - 1 - p0;
+            if (b_hi > W - 1) b_hi = W - 1;
+            if (b_lo > b_hi) continue;
+            const C fr = rec_frac[r];
+            const C v = rec_vis[r];
+            R gx[kMaxSupport];
+#pragma unroll
+            for (int a = 0; a < kMaxSupport; ++a)
+                if (a < W) gx[a] = kb_tap<R>(kbc, a, fr.x);
+            for (int b = b_lo; b <= b_hi; ++b) {
+                const R gy = kb_tap<R>(kbc, b, fr.y);
+                const R vr = v.x * gy, vi = v.y * gy;
+                const int lrow = (p0 + b - row0) << LOG2N;
+#pragma unroll
+                for (int a = 0; a < kMaxSupport; ++a) {
+                    if (a < W) {
+                        C* dst = &lds[lds_pad(lrow + ((q0 + a + shift) & nmask))];
+                        atomicAdd(&dst->x, vr * gx[a]);
+                        atomicAdd(&dst->y, vi * gx[a]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    if constexpr (FFT) {
+        fft_rows_lds<LOG2N, H, NT>(lds, tw);
+        // column-block layout [k][jb][p'][B], p' = (p + n/2) mod n: the next pass reads a
+        // contiguous [n][B] block per plane.  Image column j takes FFT bin (j + n/2) mod n.
+        constexpr int B = SH::B, LOG2B = Log2Of<B>::value_any;
+        const int pp0 = (row0 + (n >> 1)) & nmask;
+        C* dst = out + ((size_t)k << (2 * LOG2N));
+        constexpr int LHB = LOG2H + LOG2B;
+        for (int e = tid; e < elems; e += NT) {
+            const int jb = e >> LHB;
+            const int rem = e & ((1 << LHB) - 1);
+            const int lr = rem >> LOG2B, c = rem & (B - 1);
+            const int jp = (((jb << LOG2B) + c) + (n >> 1)) & nmask;
+            dst[(((size_t)jb << LOG2N) + pp0 + lr) * B + c] = lds[lds_pad((lr << LOG2N) + jp)];
+        }
+    } else {
+        C* dst = out + ((size_t)k << (2 * LOG2N)) + ((size_t)row0 << LOG2N);
+        for (int e = tid; e < elems; e += NT) dst[e] = lds[lds_pad(e)];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// column FFTs, w-phase, stacking over planes, taper
+//
+// Work-group = one block of B image columns, 16 pixels per thread.  Per plane:
+//   * the inputs of the first radix-16 pass come straight from HBM into registers (thread
+//     tid = b * B + c takes column c at rows b + m N/16, so a wave reads 64 consecutive
+//     elements of the contiguous [n][B] block); rows of empty strips read as 0;
+//   * the middle passes run in LDS, the last pass leaves its outputs in registers;
+//   * each output is multiplied by exp(+2 pi i w_k (n - 1)) and its real part summed over
+//     planes (Kahan-compensated in float, plain in double);
+//   * in float, the next plane's first-pass inputs are loaded while this plane is transformed.
+// At the end: divide by the taper on both axes and by the sum of weights.
+
+template <typename R> struct Pass2Prefetch { static constexpr bool value = sizeof(R) == 4; };
+
+template <typename R, int LOG2N, int B>
+__device__ __forceinline__ void pass2_load(const typename Cx<R>::T* __restrict__ src,
+                                           const uint8_t* __restrict__ occk, int tid, bool active,
+                                           int log2H, typename Cx<R>::T* x) {
+    using C = typename Cx<R>::T;
+    constexpr int n = 1 << LOG2N, hn = n >> 1, n16 = n >> 4;
+    const int b = tid / B;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        x[m] = cmake<C>((R)0, (R)0);
+        const int pp = b + m * n16;
+        const int p = (pp + hn) & (n - 1);
+        if (active && occk[p >> log2H]) x[m] = src[m * n16 * B + tid];
+    }
+}
+
+template <typename R, int LOG2N>
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT2))
+k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ occ,
+             const uint8_t* __restrict__ plane_occ, const typename Cx<R>::T* __restrict__ inter,
+             const typename Cx<R>::T* __restrict__ tw, const R* __restrict__ inv_taper,
+             R* __restrict__ image) {
+    using C = typename Cx<R>::T;
+    using SH = Shape<R, LOG2N>;
+    constexpr int n = SH::N, nmask = n - 1, hn = n >> 1;
+    constexpr int B = SH::B, NT = SH::NT2, LOG2B = Log2Of<B>::value_any;
+    constexpr int elems = B * n;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    // n - 1 of each output slot: in LDS after the FFT buffer (nm1s[s * NT + tid]) when it
+    // fits there, else in registers
+    double* nm1s = reinterpret_cast<double*>(lds + SH::LDS2);
+    double nm1r[SH::NM1_LDS ? 1 : 16];
+    nm1r[0] = 0.0;
+    const int jb = blockIdx.x;
+    const int tid = threadIdx.x;
+    const bool first_active = tid < (elems >> 4);
+
+    // comp is the Kahan compensation (float only)
+    R acc[16], comp[sizeof(R) == 4 ? 16 : 1];
+    comp[0] = (R)0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        acc[s] = (R)0;
+        if constexpr (sizeof(R) == 4) comp[s] = (R)0;
+        int c, ip;
+        double v = 0.0;
+        if (last_slot<LOG2N, B, NT>(tid, s, c, ip)) {
+            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + c;
+            const double l = (double)(j - hn) * g.pixel, m = (double)(i - hn) * g.pixel;
+            const double r2 = m * m + l * l;
+            v = -r2 / (1.0 + sqrt(1.0 - r2));
+        }
+        if constexpr (SH::NM1_LDS) nm1s[s * NT + tid] = v;
+        else nm1r[s] = v;
+    }
+    const double w_lo = sc->w_lo, dw = sc->dw, sum_w = sc->sum_w;
+
+    int k = 0;
+    while (k < g.nw && !plane_occ[k]) ++k;
+    C x[16], pf[16];
+    if (k < g.nw)
+        pass2_load<R, LOG2N, B>(inter + ((size_t)k << (2 * LOG2N)) + (size_t)jb * elems,
+                                occ + (size_t)k * g.S, tid, first_active, g.log2H, pf);
+    while (k < g.nw) {
+        int kn = k + 1;
+        while (kn < g.nw && !plane_occ[kn]) ++kn;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) x[m] = pf[m];
+        if constexpr (Pass2Prefetch<R>::value) {
+            if (kn < g.nw)
+                pass2_load<R, LOG2N, B>(inter + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
+                                        occ + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
+        }
+        if constexpr (LOG2N > 4) {
+            // first pass: radix 16 with L = 1 (no twiddles), registers to LDS
+            if (first_active) {
+                dft16(x);
+                const int c = tid % B, b = tid / B;
+                const int base = (c << LOG2N) + (b << 4);
+#pragma unroll
+                for (int m = 0; m < 16; ++m) lds[lds_pad(base + m)] = x[m];
+            }
+            __syncthreads();
+            stockham_range<LOG2N, 4, FftPlan<LOG2N>::LAST_L, B, NT>(lds, tw);
+            fft_last_to_regs<LOG2N, B, NT>(lds, tw, x);
+        } else {
+            if (first_active) dft16(x);   // n = 16: one pass, x[m] is bin m of column tid
+        }
+        double wk;
+        {
+#pragma clang fp contract(off)
+            wk = w_lo + ((double)k + 0.5) * dw;
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            double cyc = wk * (SH::NM1_LDS ? nm1s[s * NT + tid] : nm1r[SH::NM1_LDS ? 0 : s]);
+            cyc -= rint(cyc);
+            R sn, cs;
+            sincos_turn((R)cyc, &sn, &cs);
+            const R val = x[s].x * cs - x[s].y * sn;
+            if constexpr (sizeof(R) == 4) {
+                const R y = val - comp[s];
+                const R tt = acc[s] + y;
+                comp[s] = (tt - acc[s]) - y;
+                acc[s] = tt;
+            } else {
+                acc[s] += val;
+            }
+        }
+        if constexpr (!Pass2Prefetch<R>::value) {
+            if (kn < g.nw)
+                pass2_load<R, LOG2N, B>(inter + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
+                                        occ + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
+        }
+        __syncthreads();
+        k = kn;
+    }
+
+    const R inv_sw = sum_w > 0.0 ? (R)(1.0 / sum_w) : (R)0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        int c, ip;
+        if (last_slot<LOG2N, B, NT>(tid, s, c, ip)) {
+            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + c;
+            image[(size_t)i * n + j] = sum_w > 0.0 ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
+        }
+    }
+}
+
+}  // namespace wsimg

@@ -1,0 +1,294 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: the float32 path must match the float64 oracle to 1e-5 in both relative L2
+and relative peak error over the compared pixels; the float64 path to 1e-12.  Gridding
+alone (float64) to 1e-12 of the largest cell, float32 to 2e-6.  Integer outputs (counts,
+kept/dropped rows) must match exactly.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-12}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _dev(ds, torch):
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(np.ascontiguousarray(ds.uvw_m)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(ds.vis)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(ds.weights)).to(dev))
+
+
+def _errs(a, ref):
+    d = a - ref
+    return (float(np.linalg.norm(d) / np.linalg.norm(ref)), float(np.max(np.abs(d)) / np.max(np.abs(ref))))
+
+
+def _prm(oracle, ds, nw=None, w_range=None):
+    lo, hi = (None, None) if w_range is None else w_range
+    return oracle.Params(ds.n, ds.pixel_rad, ds.n_wplanes if nw is None else nw, ds.support, ds.beta, lo, hi)
+
+
+def _random_ds(seed, m, n, nw, W, prec, frac=0.4, wscale=300.0, dl=None):
+    """A random visibility set whose footprints cover most of an n x n grid."""
+    import synth
+    rng = np.random.default_rng(seed)
+    dl = dl if dl is not None else 2.0 / (n * 60.0)        # small field
+    freq = 1.0e9
+    lam = synth.C_LIGHT / freq
+    du = 1.0 / (n * dl)
+    uv = rng.uniform(-frac * n, frac * n, size=(m, 2)) * du * lam
+    w = rng.normal(0, 1, m) * wscale * lam
+    uvw = np.column_stack([uv, w])
+    vis = rng.normal(size=m) + 1j * rng.normal(size=m)
+    wts = rng.uniform(0.2, 2.0, m)
+    ds = synth.Dataset("random", uvw, vis, wts, freq, n, dl, nw, W, 2.34 * W)
+    return ds.as_precision(prec)
+
+
+# ---------------------------------------------------------------------------------------
+# the gridding step alone (S1-S3)
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_grid_parity_c1(oracle_mod, c1, prec):
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision(prec)
+    g, st = ws.grid(*_dev(ds, torch), ds.freq_hz, n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes,
+                    support=ds.support, beta=ds.beta, stats=True)
+    g = g.cpu().numpy()
+    pr = oracle_mod.prepare(ds.uvw_m, ds.weights, ds.freq_hz, _prm(oracle_mod, ds))
+    ref = oracle_mod.grid_stack(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, _prm(oracle_mod, ds), prepared=pr)
+    assert st["n_gridded"] == pr.n_kept and st["n_dropped"] == ds.m - pr.n_kept
+    assert st["w_lo"] == pr.w_lo and st["w_hi"] == pr.w_hi
+    assert abs(st["sum_w"] - pr.sum_w) <= 1e-12 * pr.sum_w
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(g - ref)) / scale
+    assert err <= (1e-12 if prec == "f64" else 2e-6), err
+    # every non-zero cell of the oracle is non-zero here and vice versa (same taps)
+    assert np.array_equal(np.abs(ref) > 0, np.abs(g) > 0)
+
+
+@pytest.mark.parametrize("n,nw,W,m", [(16, 1, 3, 50), (64, 3, 15, 3000), (512, 5, 9, 20000)])
+def test_grid_parity_shapes(oracle_mod, n, nw, W, m):
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = _random_ds(11 + n, m, n, nw, W, "f64")
+    g = ws.grid(*_dev(ds, torch), ds.freq_hz, n=n, pixel_rad=ds.pixel_rad, n_wplanes=nw, support=W,
+                beta=ds.beta).cpu().numpy()
+    ref = oracle_mod.grid_stack(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, _prm(oracle_mod, ds))
+    assert np.max(np.abs(g - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------------------
+# the whole path (S1-S6)
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_image_parity_c1(oracle_mod, c1, prec):
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision(prec)
+    img = ws.image(*_dev(ds, torch), ds.freq_hz, n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes,
+                   support=ds.support, beta=ds.beta).cpu().numpy()
+    ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, _prm(oracle_mod, ds))
+    l2, pk = _errs(img, ref)
+    print(f"c1 {prec}: rel_l2={l2:.3e} rel_peak={pk:.3e}")
+    assert l2 <= TOL[prec] and pk <= TOL[prec]
+
+
+@pytest.mark.parametrize("n,nw,W,m", [
+    (16, 1, 3, 40), (32, 2, 5, 500), (64, 3, 7, 4000), (128, 4, 15, 5000),
+    (256, 7, 9, 30000), (512, 5, 7, 60000), (1024, 3, 7, 100000), (2048, 2, 9, 50000),
+])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_image_parity_shapes(oracle_mod, n, nw, W, m, prec):
+    """Every transform size that takes a different pass layout, ragged strip and block counts."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = _random_ds(100 + n + nw, m, n, nw, W, prec)
+    img = ws.image(*_dev(ds, torch), ds.freq_hz, n=n, pixel_rad=ds.pixel_rad, n_wplanes=nw, support=W,
+                   beta=ds.beta).cpu().numpy()
+    ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, _prm(oracle_mod, ds))
+    l2, pk = _errs(img, ref)
+    assert l2 <= TOL[prec] and pk <= TOL[prec], (l2, pk)
+
+
+def test_fixed_range_and_clamping(oracle_mod):
+    """A fixed plane range narrower than the data: rows beyond it go to the edge planes."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = _random_ds(7, 20000, 256, 6, 7, "f64", wscale=2000.0)
+    wr = (-500.0, 800.0)
+    img = ws.image(*_dev(ds, torch), ds.freq_hz, n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=6, support=7,
+                   beta=ds.beta, w_range=wr).cpu().numpy()
+    ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, _prm(oracle_mod, ds, w_range=wr))
+    l2, pk = _errs(img, ref)
+    assert l2 <= 1e-12 and pk <= 1e-12
+
+
+def test_drops_counts_and_nonfinite(oracle_mod):
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = _random_ds(8, 5000, 128, 4, 7, "f64", frac=0.55)       # some footprints leave the grid
+    ds.uvw_m[10, 0] = np.nan
+    ds.uvw_m[11, 2] = np.inf
+    ds.weights[12] = np.nan
+    ds.weights[13] = 0.0
+    img, st = ws.image(*_dev(ds, torch), ds.freq_hz, n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=4,
+                       support=7, beta=ds.beta, stats=True)
+    pr = oracle_mod.prepare(ds.uvw_m, ds.weights, ds.freq_hz, _prm(oracle_mod, ds))
+    assert 0 < st["n_dropped"] == ds.m - pr.n_kept
+    assert st["n_gridded"] == pr.n_kept
+    ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, _prm(oracle_mod, ds))
+    l2, pk = _errs(img.cpu().numpy(), ref)
+    assert l2 <= 1e-12 and pk <= 1e-12
+
+
+def test_empty_inputs():
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    dev = torch.device("cuda:0")
+    p = ws.Plan(64, 1e-4, 4, 7, precision="f32", max_vis=10)
+    uvw = torch.zeros((0, 3), dtype=torch.float64, device=dev)
+    vis = torch.zeros(0, dtype=torch.complex64, device=dev)
+    w = torch.zeros(0, dtype=torch.float32, device=dev)
+    out = torch.full((64, 64), 7.0, device=dev)
+    with pytest.raises(ws.WsimgError) as e:
+        p.image(uvw, vis, w, 1e9, out=out, stats=True)
+    assert e.value.status == -4
+    assert not torch.any(out != 0)
+    # all rows off the grid
+    uvw = torch.tensor([[1e9, 0.0, 0.0]] * 3, dtype=torch.float64, device=dev)
+    vis = torch.ones(3, dtype=torch.complex64, device=dev)
+    w = torch.ones(3, dtype=torch.float32, device=dev)
+    out.fill_(3.0)
+    with pytest.raises(ws.WsimgError):
+        p.image(uvw, vis, w, 1e9, out=out, stats=True)
+    assert not torch.any(out != 0)
+    # capacity
+    big = torch.zeros((11, 3), dtype=torch.float64, device=dev)
+    with pytest.raises(ws.WsimgError) as e:
+        p.image(big, torch.zeros(11, dtype=torch.complex64, device=dev),
+                torch.zeros(11, dtype=torch.float32, device=dev), 1e9)
+    assert e.value.status == -5
+    p.close()
+
+
+def test_hot_bucket_and_single_cell(oracle_mod):
+    """Many rows on one cell (one overfull bucket) next to a sparse background."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = _random_ds(9, 40000, 256, 3, 7, "f32")
+    ds.uvw_m[:30000, :2] = ds.uvw_m[0, :2]
+    img = ws.image(*_dev(ds, torch), ds.freq_hz, n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=3, support=7,
+                   beta=ds.beta).cpu().numpy()
+    ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, _prm(oracle_mod, ds))
+    l2, pk = _errs(img, ref)
+    assert l2 <= 1e-5 and pk <= 1e-5
+
+
+def test_point_source_through_gpu(oracle_mod, c1):
+    """The DFT pin of a point source carried over: the GPU image peaks on the source pixel
+    with F/n0 within the w-quantisation and aliasing bound."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    n, dl = c1.n, c1.pixel_rad
+    i0, j0 = n // 2 + 23, n // 2 - 41
+    l0, m0 = (j0 - n // 2) * dl, (i0 - n // 2) * dl
+    u, v, w = (c1.uvw_m * c1.freq_hz / 299_792_458.0).T
+    n0 = math.sqrt(1 - l0 * l0 - m0 * m0)
+    vis = (0.9 / n0) * np.exp(-2j * math.pi * (u * l0 + v * m0 + w * (n0 - 1)))
+    ds = c1.__class__(**{**c1.__dict__, "vis": vis.astype(np.complex64), "weights": c1.weights.astype(np.float32)})
+    img = ws.image(*_dev(ds, torch), ds.freq_hz, n=n, pixel_rad=dl, n_wplanes=16, support=7,
+                   beta=ds.beta).cpu().numpy()
+    assert np.unravel_index(np.argmax(img), img.shape) == (i0, j0)
+    assert abs(img[i0, j0] * n0 / 0.9 - 1.0) < 1e-3
+
+
+def test_repeat_calls_and_timing(c1):
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision("f32")
+    args = _dev(ds, torch)
+    with ws.Plan(ds.n, ds.pixel_rad, ds.n_wplanes, ds.support, ds.beta, "f32", max_vis=ds.m) as p:
+        p.set_timing(True)
+        a = p.image(*args, ds.freq_hz).cpu().numpy()
+        b = p.image(*args, ds.freq_hz).cpu().numpy()
+        t = p.read_timing()
+        info = p.info()
+    assert t["calls"] == 2 and t["ms_total"] > 0 and all(v >= 0 for v in t["ms"].values())
+    assert np.max(np.abs(a - b)) <= 1e-6 * np.max(np.abs(a))
+    assert info["n"] == ds.n and info["device_bytes"] > 0
+
+
+# ---------------------------------------------------------------------------------------
+# full-size workloads: sampled pixels against the oracle, whole image float32 vs float64
+
+def _sample_pixels(n, k, seed):
+    rng = np.random.default_rng(seed)
+    inner = np.arange(n // 4, 3 * n // 4)
+    rows = np.sort(rng.choice(inner, k, replace=False))
+    cols = np.sort(rng.choice(inner, k, replace=False))
+    rows[0], cols[0] = n // 2, n // 2                 # include the phase centre
+    return rows, cols
+
+
+@pytest.mark.slow
+def test_c2_full_size(oracle_mod):
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    import synth
+    ds = synth.make_config(2, device="cuda")
+    args32 = _dev(ds, torch)
+    d64 = ds.as_precision("f64")
+    args64 = _dev(d64, torch)
+    kw = dict(n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta)
+    img32 = ws.image(*args32, ds.freq_hz, **kw).cpu().numpy()
+    img64 = ws.image(*args64, ds.freq_hz, **kw).cpu().numpy()
+    l2, pk = _errs(img32, img64)
+    print(f"c2 f32 vs gpu f64: rel_l2={l2:.3e} rel_peak={pk:.3e}")
+    assert l2 <= 1e-5 and pk <= 1e-5
+    rows, cols = _sample_pixels(ds.n, 12, 2)
+    ref = oracle_mod.wstack_image(d64.uvw_m, d64.vis, d64.weights, d64.freq_hz, _prm(oracle_mod, d64),
+                                  pixels=(rows, cols))
+    scale = np.max(np.abs(img64))   # errors relative to the image peak
+    e64 = np.max(np.abs(img64[np.ix_(rows, cols)] - ref)) / scale
+    e32 = np.max(np.abs(img32[np.ix_(rows, cols)] - ref)) / scale
+    print(f"c2 sampled vs oracle: f64 {e64:.3e} f32 {e32:.3e}")
+    assert e64 <= 1e-12 and e32 <= 1e-5
+
+
+@pytest.mark.slow
+def test_c3_geometry_full_grid(oracle_mod):
+    """The 8192^2, 64-plane, W = 9 geometry at a shortened track (2^21 rows): sampled pixels
+    against the oracle; whole image float32 against float64."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    import synth
+    ds = synth.make_config(3, device="cuda", max_rows=1 << 21)
+    d64 = ds.as_precision("f64")
+    kw = dict(n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta)
+    img32 = ws.image(*_dev(ds, torch), ds.freq_hz, **kw).cpu().numpy()
+    img64 = ws.image(*_dev(d64, torch), ds.freq_hz, **kw).cpu().numpy()
+    l2, pk = _errs(img32, img64)
+    print(f"c3 f32 vs gpu f64: rel_l2={l2:.3e} rel_peak={pk:.3e}")
+    assert l2 <= 1e-5 and pk <= 1e-5
+    rows, cols = _sample_pixels(ds.n, 8, 3)
+    ref = oracle_mod.wstack_image(d64.uvw_m, d64.vis, d64.weights, d64.freq_hz, _prm(oracle_mod, d64),
+                                  pixels=(rows, cols))
+    scale = np.max(np.abs(img64))
+    e64 = np.max(np.abs(img64[np.ix_(rows, cols)] - ref)) / scale
+    e32 = np.max(np.abs(img32[np.ix_(rows, cols)] - ref)) / scale
+    print(f"c3 sampled vs oracle: f64 {e64:.3e} f32 {e32:.3e}")
+    assert e64 <= 1e-12 and e32 <= 1e-5
