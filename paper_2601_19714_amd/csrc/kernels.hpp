@@ -234,13 +234,14 @@ k_scatter(int64_t M, const double* __restrict__ uvw, const typename Cx<R>::T* __
 
 // ---------------------------------------------------------------------------------------
 // Work-group shapes, fixed per (precision, image size).
-//   pass 1: H grid rows per strip, H * N <= 16384 (float) / 8192 (double) complex in LDS,
-//           NT1 = H * N / 16 threads (one radix-16 butterfly each per pass);
+//   pass 1: H grid rows per strip; the strip accumulates in float64 (16 B per cell) whatever
+//           the precision, so H * N <= 8192 cells; NT1 = H * N / 16 threads (one radix-16
+//           butterfly each per pass);
 //   pass 2: B image columns per block, B * N = 8192 (float) / 4096 (double) pixels,
 //           NT2 = B * N / 16 threads (16 output pixels each).
 template <typename R, int LOG2N> struct Shape {
     static constexpr int N = 1 << LOG2N;
-    static constexpr int CAP1 = sizeof(R) == 4 ? 16384 : 8192;
+    static constexpr int CAP1 = 8192;
     static constexpr int H0 = CAP1 / N < 32 ? CAP1 / N : 32;
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
     static constexpr int NT1 = (H * N / 16) < 64 ? 64 : (H * N / 16);
@@ -248,7 +249,8 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int B0 = PX2 / N < N ? PX2 / N : N;
     static constexpr int B = B0 < 1 ? 1 : B0;
     static constexpr int NT2 = (B * N / 16) < 64 ? 64 : (B * N / 16);
-    static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // complex elements
+    static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
+    static constexpr size_t LDS1_BYTES = (size_t)LDS1 * sizeof(double2);   // float64 accumulation
     static constexpr int LDS2 = lds_padded_elems_c(B * N);                 // complex elements
     // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer
     static constexpr bool NM1_LDS =
@@ -260,6 +262,11 @@ template <typename R, int LOG2N> struct Shape {
 // ---------------------------------------------------------------------------------------
 // gridding (+ row FFT) of one (plane, strip) in LDS
 
+// The strip's cells accumulate in float64 in LDS for both precisions: with no grid padding
+// the taper division amplifies grid rounding near the image edge by up to 1/C(1/2)^2 (about
+// 2500 for W = 7), and float32 atomic accumulation alone costs ~1e-5 of the image there.
+// The per-tap products are formed in the plan's precision; the float path converts the
+// strip to float32 in place before its FFT.
 template <typename R, bool FFT, int LOG2N>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
 k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restrict__ occ,
@@ -272,6 +279,7 @@ k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
     constexpr int LOG2H = Log2Of<H>::value_any;
     constexpr int elems = H * n;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    double2* acc = reinterpret_cast<double2*>(smem_raw);
     C* lds = reinterpret_cast<C*>(smem_raw);
     const int nblk = g.nw * g.S;
     const int logical = xcd_remap(blockIdx.x, nblk);
@@ -285,7 +293,7 @@ k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
         }
         return;
     }
-    for (int e = tid; e < SH::LDS1; e += NT) lds[e] = cmake<C>((R)0, (R)0);
+    for (int e = tid; e < SH::LDS1; e += NT) acc[e] = make_double2(0.0, 0.0);
     __syncthreads();
 
     const int W = g.support;
@@ -315,9 +323,9 @@ k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
 #pragma unroll
                 for (int a = 0; a < kMaxSupport; ++a) {
                     if (a < W) {
-                        C* dst = &lds[lds_pad(lrow + ((q0 + a + shift) & nmask))];
-                        atomicAdd(&dst->x, vr * gx[a]);
-                        atomicAdd(&dst->y, vi * gx[a]);
+                        double2* dst = &acc[lds_pad(lrow + ((q0 + a + shift) & nmask))];
+                        atomicAdd(&dst->x, (double)(vr * gx[a]));
+                        atomicAdd(&dst->y, (double)(vi * gx[a]));
                     }
                 }
             }
@@ -326,6 +334,23 @@ k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
     __syncthreads();
 
     if constexpr (FFT) {
+        if constexpr (sizeof(R) == 4) {
+            // float64 strip -> float32 strip in the same LDS (all reads before any write)
+            constexpr int PER = (elems + NT - 1) / NT;
+            double2 t[PER];
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int e = tid + i * NT;
+                if (e < elems) t[i] = acc[lds_pad(e)];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int e = tid + i * NT;
+                if (e < elems) lds[lds_pad(e)] = cmake<C>((R)t[i].x, (R)t[i].y);
+            }
+            __syncthreads();
+        }
         fft_rows_lds<LOG2N, H, NT>(lds, tw);
         // column-block layout [k][jb][p'][B], p' = (p + n/2) mod n: the next pass reads a
         // contiguous [n][B] block per plane.  Image column j takes FFT bin (j + n/2) mod n.
@@ -342,7 +367,10 @@ k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
         }
     } else {
         C* dst = out + ((size_t)k << (2 * LOG2N)) + ((size_t)row0 << LOG2N);
-        for (int e = tid; e < elems; e += NT) dst[e] = lds[lds_pad(e)];
+        for (int e = tid; e < elems; e += NT) {
+            const double2 a = acc[lds_pad(e)];
+            dst[e] = cmake<C>((R)a.x, (R)a.y);
+        }
     }
 }
 

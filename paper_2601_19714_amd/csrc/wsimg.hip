@@ -157,7 +157,7 @@ wsimg_status configure_shape(wsimg_plan* pl) {
     g.B = SH::B; g.log2B = Log2Of<SH::B>::value_any; g.NB = SH::N / SH::B;
     pl->nt1 = SH::NT1;
     pl->nt2 = SH::NT2;
-    pl->lds1 = (size_t)SH::LDS1 * sizeof(typename Cx<R>::T);
+    pl->lds1 = SH::LDS1_BYTES;
     pl->lds2 = SH::LDS2_BYTES;
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, true, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
