@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of the w-stacking imager on one MI355X: visibilities imaged per second.
+
+A step is one whole dirty image (all stages: bucket sort, gridding + row FFT, column
+FFT + w-phase + stacking + taper) of one synthetic visibility set already resident in HBM.
+The default workload is the MeerKAT-shaped single channel: 7 257 600 visibilities,
+4096^2 image, 32 w-planes, Kaiser-Bessel support 7, float32 path; the float64 path is
+timed on the same inputs and its rate and the float32/float64 speedup are reported too.
+
+Prints ONE JSON line.  Extra objects:
+  roofline     : the dominant kernel's algorithmic bytes (or flops) per launch over its
+                 average duration, from HIP events recorded on the plan's stream during
+                 the timed steps, against the MI355X peak;
+  cpu_baseline : the FP64 oracle timed on a bounded sample of the same workload on the
+                 host cores (test infrastructure, run only here, rank 0, N = 1).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "visibilities imaged/s (FP32 vs FP64 path, 1 GPU) at ≤1e-5 rel err vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector, published (includes packed issue)
+WORKLOADS = {"c1": 1, "c2": 2, "c3": 3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2601_19714_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_traffic(prec: str, n: int, m_kept: int, n_occ: int, strip_rows: int):
+    """Bytes each stage must move (not sort scratch re-reads), per call."""
+    cb = 8 if prec == "f32" else 16          # complex element
+    rb = cb // 2
+    rec = 4 + cb + cb                        # record: cell id, sub-cell offsets, W*V
+    inter = n_occ * strip_rows * n * cb      # row-transformed occupied strips
+    return {
+        "grid_rows": m_kept * rec + inter,                   # records in, strips out
+        "cols_stack": inter + n * n * rb,                    # strips in, image out
+    }
+
+
+def cols_stack_flops(n: int, nw_occ: int) -> float:
+    """Algorithmic flops of the stacking pass: a length-n column FFT per image column and
+    plane (5 n log2 n) and a complex multiply by the w-phase plus the accumulate (8)."""
+    return nw_occ * n * (5.0 * n * math.log2(n) + 8.0 * n)
+
+
+def run_gpu(ds, prec: str, steps: int, warmup: int):
+    import torch
+    import paper_2601_19714_amd as ws
+
+    d = ds.as_precision(prec)
+    dev = torch.device("cuda:0")
+    uvw = torch.from_numpy(d.uvw_m).to(dev)
+    vis = torch.from_numpy(d.vis).to(dev)
+    wts = torch.from_numpy(d.weights).to(dev)
+    plan = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, prec, max_vis=d.m)
+    out = torch.empty((d.n, d.n), dtype=torch.float32 if prec == "f32" else torch.float64, device=dev)
+    _, st = plan.image(uvw, vis, wts, d.freq_hz, out=out, stats=True)
+    for _ in range(warmup):
+        plan.image(uvw, vis, wts, d.freq_hz, out=out)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.image(uvw, vis, wts, d.freq_hz, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    timing = plan.read_timing()
+    plan.set_timing(False)
+    info = plan.info()
+    img = out.cpu().numpy()
+    plan.close()
+    return {"ms_per_step": 1e3 * wall / steps, "timing": timing, "stats": st, "info": info, "image": img}
+
+
+def cpu_baseline(ds, n_sample_planes: int):
+    """The oracle on a stratified sample of w-planes, scaled to the whole workload:
+    vis/s = M / (T_prepare + (Nw / n_sample) * T_sampled_planes)."""
+    import numpy as np
+    import oracle
+    d = ds.as_precision("f64")
+    prm = oracle.Params(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta)
+    t0 = time.perf_counter()
+    pr = oracle.prepare(d.uvw_m, d.weights, d.freq_hz, prm)
+    t_prep = time.perf_counter() - t0
+    step = max(1, d.n_wplanes // n_sample_planes)
+    planes = list(range(0, d.n_wplanes, step))[:n_sample_planes]
+    t0 = time.perf_counter()
+    oracle.wstack_image(d.uvw_m, d.vis, d.weights, d.freq_hz, prm, planes=planes, prepared=pr)
+    t_planes = time.perf_counter() - t0
+    est = t_prep + (d.n_wplanes / len(planes)) * t_planes
+    m_sample = int(np.isin(pr.k[pr.keep], planes).sum())
+    return {
+        "value": d.m / est, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 oracle (steps 1-3 on all {d.m} rows: {t_prep:.2f} s; steps 4-8 on w-planes "
+                   f"{planes} of {d.n_wplanes}, {m_sample} rows: {t_planes:.2f} s), whole-image time "
+                   f"estimated as prepare + {d.n_wplanes}/{len(planes)} x sampled planes = {est:.1f} s; "
+                   f"single-threaded numpy FFT and C gridding loop"),
+    }
+
+
+def read_pmc_traffic(kernel: str, workload: str, src_hash: str):
+    """HBM bytes per dispatch from a committed rocprofv3 PMC summary, if it was taken on
+    the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != src_hash:
+        return None
+    return rec.get("hbm_bytes_per_dispatch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--no-f64", action="store_true", help="skip the float64 path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-planes", type=int, default=4)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this imager runs on a single device (multi-GPU sharding "
+              "is a design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+
+    cfg = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    ds = synth.make_config(cfg, device="cuda" if torch.cuda.is_available() else "cpu")
+    log(f"generated {ds.name}: M={ds.m} n={ds.n} nw={ds.n_wplanes} W={ds.support} "
+        f"in {time.perf_counter() - t0:.1f}s")
+
+    r32 = run_gpu(ds, "f32", args.steps, args.warmup)
+    log(f"f32: {r32['ms_per_step']:.3f} ms/step  stages(ms/call) " +
+        ", ".join(f"{k}={v / max(1, r32['timing']['calls']):.4f}" for k, v in r32["timing"]["ms"].items()))
+    r64 = None
+    if not args.no_f64:
+        r64 = run_gpu(ds, "f64", args.steps, args.warmup)
+        log(f"f64: {r64['ms_per_step']:.3f} ms/step  stages(ms/call) " +
+            ", ".join(f"{k}={v / max(1, r64['timing']['calls']):.4f}" for k, v in r64["timing"]["ms"].items()))
+
+    m = ds.m
+    value = m / (r32["ms_per_step"] / 1e3)
+    st = r32["stats"]
+    calls = max(1, r32["timing"]["calls"])
+    per_call = {k: v / calls for k, v in r32["timing"]["ms"].items()}
+    dominant = max(per_call, key=per_call.get)
+    nw_occ = st["n_planes_occupied"]
+    traffic = algorithmic_traffic("f32", ds.n, st["n_gridded"], st["n_strips_occupied"], r32["info"]["strip_rows"])
+    src_hash = kernel_source_hash()
+    roof = None
+    if dominant in traffic:
+        achieved_gbs = traffic[dominant] / (per_call[dominant] / 1e3) / 1e9
+        roof_hbm = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved_gbs / HBM_PEAK_GBS}
+        roof = roof_hbm
+        if dominant == "cols_stack":
+            tf = cols_stack_flops(ds.n, nw_occ) / (per_call[dominant] / 1e3) / 1e12
+            roof_alu = {"bound": "alu", "achieved": tf, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / FP32_VECTOR_PEAK_TFLOPS}
+            if roof_alu["frac"] > roof_hbm["frac"]:
+                roof = roof_alu
+        roof["kernel"] = dominant
+        roof["ms_per_launch"] = per_call[dominant]
+        roof["traffic"] = read_pmc_traffic(dominant, ds.name, src_hash)
+        roof["algorithmic_bytes"] = traffic[dominant]
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ds.name, "n_vis": m, "n": ds.n, "n_wplanes": ds.n_wplanes,
+                   "support": ds.support, "beta": ds.beta, "pixel_arcsec": ds.pixel_rad / synth.ARCSEC,
+                   "freq_hz": ds.freq_hz, "precision": "f32"},
+        "stage_ms": per_call,
+        "occupancy": {"strips_occupied": st["n_strips_occupied"],
+                      "strips_total": ds.n_wplanes * ds.n // r32["info"]["strip_rows"],
+                      "strip_rows": r32["info"]["strip_rows"], "planes_occupied": nw_occ},
+        "roofline": roof,
+        "kernel_source_hash": src_hash,
+    }
+    if r64 is not None:
+        res["f64_value"] = m / (r64["ms_per_step"] / 1e3)
+        res["f64_ms_per_step"] = r64["ms_per_step"]
+        res["speedup_f32_over_f64"] = r64["ms_per_step"] / r32["ms_per_step"]
+        a, b = r32["image"].astype(np.float64), r64["image"]
+        res["f32_vs_f64_full_image"] = {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                                        "rel_peak": float(np.max(np.abs(a - b)) / np.max(np.abs(b)))}
+        c = slice(ds.n // 2 - 256, ds.n // 2 + 256)
+        res["f32_vs_f64_central_512"] = {
+            "rel_l2": float(np.linalg.norm(a[c, c] - b[c, c]) / np.linalg.norm(b[c, c])),
+            "rel_peak": float(np.max(np.abs(a[c, c] - b[c, c])) / np.max(np.abs(b[c, c])))}
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a sample of planes ...")
+        res["cpu_baseline"] = cpu_baseline(ds, args.cpu_sample_planes)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,6 +75,9 @@ typedef struct {
     int64_t n_dropped;  /* n_in - n_gridded                                                */
     double sum_w;       /* sum of the kept weights (the image is divided by it)           */
     double w_lo, w_hi;  /* plane range used                                                */
+    int64_t n_strips_occupied;  /* (w-plane, row strip) pairs holding at least one tap: only
+                                   these strips are transformed and stored between the passes */
+    int64_t n_planes_occupied;  /* w-planes holding at least one kept row                      */
 } wsimg_stats;
 
 typedef struct {

@@ -37,7 +37,8 @@ class Params(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_in", ctypes.c_int64), ("n_gridded", ctypes.c_int64), ("n_dropped", ctypes.c_int64),
-                ("sum_w", ctypes.c_double), ("w_lo", ctypes.c_double), ("w_hi", ctypes.c_double)]
+                ("sum_w", ctypes.c_double), ("w_lo", ctypes.c_double), ("w_hi", ctypes.c_double),
+                ("n_strips_occupied", ctypes.c_int64), ("n_planes_occupied", ctypes.c_int64)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -35,7 +35,7 @@ struct Geom {
 // Written by k_finalize, read by the later stages.
 struct Scalars {
     double w_lo, w_hi, dw, sum_w;
-    unsigned long long n_kept, n_in;
+    unsigned long long n_kept, n_in, n_occ, n_planes;
 };
 
 struct Partial {
@@ -149,6 +149,8 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, int64_t M, Scal
         r.sum_w = s_sw[0];
         r.n_kept = s_nk[0];
         r.n_in = (unsigned long long)M;
+        r.n_occ = 0;
+        r.n_planes = 0;
         *sc = r;
     }
 }
@@ -178,7 +180,7 @@ k_key(int64_t M, const double* __restrict__ uvw, const WT* __restrict__ wts, dou
 // buckets s_lo(s)..s (the strips whose rows can reach s) is non-empty.
 __global__ void __launch_bounds__(1024)
 k_scan(int nb, const uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, Geom g,
-       uint8_t* __restrict__ occ, uint8_t* __restrict__ plane_occ) {
+       uint8_t* __restrict__ occ, uint8_t* __restrict__ plane_occ, Scalars* __restrict__ sc) {
     __shared__ uint32_t part[1024];
     const int t = threadIdx.x, nt = blockDim.x;
     const int chunk = (nb + nt - 1) / nt;
@@ -199,14 +201,37 @@ k_scan(int nb, const uint32_t* __restrict__ counts, uint32_t* __restrict__ offse
     if (t == nt - 1) offsets[nb] = part[nt - 1];
     __syncthreads();
     __threadfence_block();
+    uint32_t nocc = 0;
     for (int b = t; b < nb; b += nt) {
         const int k = b / g.S, sidx = b - k * g.S;
         int slo = ((sidx << g.log2H) - (g.support - 1)) >> g.log2H;
         if (slo < 0) slo = 0;
-        occ[b] = offsets[k * g.S + sidx + 1] > offsets[k * g.S + slo] ? 1 : 0;
+        const uint8_t o = offsets[k * g.S + sidx + 1] > offsets[k * g.S + slo] ? 1 : 0;
+        occ[b] = o;
+        nocc += o;
     }
-    for (int k = t; k < g.nw; k += nt)
-        plane_occ[k] = offsets[(k + 1) * g.S] > offsets[k * g.S] ? 1 : 0;
+    __syncthreads();
+    part[t] = nocc;
+    __syncthreads();
+    for (int o = nt >> 1; o > 0; o >>= 1) {
+        if (t < o) part[t] += part[t + o];
+        __syncthreads();
+    }
+    if (t == 0) sc->n_occ = part[0];
+    uint32_t npl = 0;
+    for (int k = t; k < g.nw; k += nt) {
+        const uint8_t o = offsets[(k + 1) * g.S] > offsets[k * g.S] ? 1 : 0;
+        plane_occ[k] = o;
+        npl += o;
+    }
+    __syncthreads();
+    part[t] = npl;
+    __syncthreads();
+    for (int o = nt >> 1; o > 0; o >>= 1) {
+        if (t < o) part[t] += part[t + o];
+        __syncthreads();
+    }
+    if (t == 0) sc->n_planes = part[0];
 }
 
 template <typename R, typename WT>

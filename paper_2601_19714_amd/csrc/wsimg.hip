@@ -295,7 +295,7 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, c
     if (auto r = st.after(2)) return r;
 
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (int)nbk, pl->counts, pl->offsets, g, pl->occ,
-                       pl->plane_occ);
+                       pl->plane_occ, pl->scalars);
     WS_LAUNCH_CHECK("scan");
     if (auto r = st.after(3)) return r;
 
@@ -340,6 +340,8 @@ wsimg_status finish_call(wsimg_plan* pl, wsimg_stats* stats) {
     stats->sum_w = h.sum_w;
     stats->w_lo = h.w_lo;
     stats->w_hi = h.w_hi;
+    stats->n_strips_occupied = (int64_t)h.n_occ;
+    stats->n_planes_occupied = (int64_t)h.n_planes;
     if (!(h.sum_w != 0.0)) return fail(WSIMG_E_EMPTY, "the kept visibilities have zero total weight");
     return WSIMG_OK;
 }
