@@ -73,14 +73,6 @@ __device__ __forceinline__ int plane_index(double w, double w_lo, double dw, int
     return (int)kf;
 }
 
-// The hardware hands work-group i to XCD (i mod 8).  Map the launch index to a logical
-// index so that consecutive logical indices land on the same XCD (and its L2).
-__device__ __forceinline__ int xcd_remap(int i, int total) {
-    const int q = total >> 3, r = total & 7;
-    const int x = i & 7, j = i >> 3;
-    return x * q + (x < r ? x : r) + j;
-}
-
 // sin(2 pi t) and cos(2 pi t) for |t| <= 1/2 (t in turns).  Quadrant reduction
 // q = rint(4t), r = t - q/4 (exact), |r| <= 1/8; then the Taylor series of sin and cos
 // of 2 pi r (error below 2e-9 in float, 5e-16 in double), and the quadrant rotation.

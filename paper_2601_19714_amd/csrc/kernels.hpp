@@ -5,8 +5,10 @@
 //  k_reduce       : per-block partial (min w, max w, sum of weights, count) over kept rows.
 //  k_finalize     : fixed-order reduction of the partials -> plane range and sum of weights.
 //  k_key          : per row, the bucket (w-plane, row strip of its first tap row) and its rank
-//                   inside the bucket (a counting-sort histogram, Sec. 3.2's bucket sort).
-//  k_scan         : exclusive scan of the bucket counts; strip and plane occupancy flags.
+//                   inside the bucket (a counting-sort histogram, Sec. 3.2's bucket sort) on
+//                   replicated counters.
+//  k_scan_*       : exclusive scan of the counters (tile sums, top level, tiles).
+//  k_occupancy    : strip and plane occupancy flags and counts.
 //  k_scatter      : sorted records {tap origin, sub-cell offsets, W*V} (SoA).
 //  k_grid_rows    : one work-group per occupied (plane, strip): Kaiser-Bessel gridding of every
 //                   record whose taps reach the strip into an LDS strip (Eq. 3), then the
@@ -155,6 +157,14 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, int64_t M, Scal
     }
 }
 
+// Bucket counters are replicated kReplicas times, laid out [bucket][replica]; row m counts
+// in replica (m >> 8) mod kReplicas.  The rows of one hot bucket (tens of thousands near the
+// uv-plane centre) then spread their atomics over kReplicas addresses instead of one, and
+// the bucket's rows still end up contiguous after the scan.
+constexpr int kReplicas = 64;
+constexpr int kLogReplicas = 6;
+__device__ __forceinline__ uint32_t row_replica(int64_t m) { return (uint32_t)(m >> 8) & (kReplicas - 1); }
+
 template <typename WT>
 __global__ void __launch_bounds__(256)
 k_key(int64_t M, const double* __restrict__ uvw, const WT* __restrict__ wts, double freq, Geom g,
@@ -169,69 +179,112 @@ k_key(int64_t M, const double* __restrict__ uvw, const WT* __restrict__ wts, dou
         const int k = plane_index(rg.w, sc->w_lo, sc->dw, g.nw);
         const int p0 = (int)rg.cy - g.half;
         kk = (uint32_t)(k * g.S + (p0 >> g.log2H));
-        rr = atomicAdd(&counts[kk], 1u);
+        rr = atomicAdd(&counts[((size_t)kk << kLogReplicas) + row_replica(m)], 1u);
     }
     key[m] = kk;
     rank[m] = rr;
 }
 
-// One block of 1024 threads: exclusive scan of nb counts, then occupancy flags.
-// occ[k*S + s] = 1 when some record of plane k has a tap row inside strip s, i.e. one of the
-// buckets s_lo(s)..s (the strips whose rows can reach s) is non-empty.
+// Exclusive scan of the replicated counters (total = nb * kReplicas entries) in three
+// kernels: tile sums, a one-block scan of the tile sums, then each tile's own scan.
+constexpr int kScanTile = 4096;     // 256 threads x 16 entries
+
+__global__ void __launch_bounds__(256)
+k_scan_tiles(int64_t total, const uint32_t* __restrict__ counts, uint32_t* __restrict__ tile_sums) {
+    __shared__ uint32_t red[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int i = 0; i < 16; ++i) {
+        const int64_t e = base + (int64_t)i * 256 + threadIdx.x;
+        if (e < total) s += counts[e];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = red[0];
+}
+
+// One block of 1024 threads over ntiles tile sums (in place: sums -> exclusive offsets).
 __global__ void __launch_bounds__(1024)
-k_scan(int nb, const uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, Geom g,
-       uint8_t* __restrict__ occ, uint8_t* __restrict__ plane_occ, Scalars* __restrict__ sc) {
+k_scan_top(int ntiles, uint32_t* __restrict__ tile_sums) {
     __shared__ uint32_t part[1024];
     const int t = threadIdx.x, nt = blockDim.x;
-    const int chunk = (nb + nt - 1) / nt;
+    const int chunk = (ntiles + nt - 1) / nt;
     const int b0 = t * chunk;
-    const int b1 = b0 + chunk < nb ? b0 + chunk : nb;
+    const int b1 = b0 + chunk < ntiles ? b0 + chunk : ntiles;
     uint32_t s = 0;
-    for (int b = b0; b < b1; ++b) s += counts[b];
+    for (int b = b0; b < b1; ++b) s += tile_sums[b];
     part[t] = s;
     __syncthreads();
-    for (int o = 1; o < nt; o <<= 1) {          // inclusive Hillis-Steele scan
+    for (int o = 1; o < nt; o <<= 1) {
         uint32_t v = t >= o ? part[t - o] : 0u;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
     uint32_t run = t > 0 ? part[t - 1] : 0u;
-    for (int b = b0; b < b1; ++b) { offsets[b] = run; run += counts[b]; }
-    if (t == nt - 1) offsets[nb] = part[nt - 1];
+    for (int b = b0; b < b1; ++b) { const uint32_t c = tile_sums[b]; tile_sums[b] = run; run += c; }
+}
+
+// Each thread scans 16 consecutive entries; the block scans the 256 thread totals.
+__global__ void __launch_bounds__(256)
+k_scan_down(int64_t total, const uint32_t* __restrict__ counts, const uint32_t* __restrict__ tile_offs,
+            uint32_t* __restrict__ offsets) {
+    __shared__ uint32_t part[256];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * 16;
+    uint32_t v[16], s = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        v[i] = base + i < total ? counts[base + i] : 0u;
+        s += v[i];
+    }
+    part[t] = s;
     __syncthreads();
-    __threadfence_block();
-    uint32_t nocc = 0;
-    for (int b = t; b < nb; b += nt) {
+    for (int o = 1; o < 256; o <<= 1) {
+        uint32_t x = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = tile_offs[blockIdx.x] + (t > 0 ? part[t - 1] : 0u);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (base + i < total) offsets[base + i] = run;
+        run += v[i];
+    }
+    if (base + 16 >= total && base < total) offsets[total] = run;   // the thread holding the last entry
+}
+
+// Strip and plane occupancy.  occ[k*S + s] = 1 when some record of plane k has a tap row
+// inside strip s, i.e. one of the buckets s_lo(s)..s (the strips whose rows can reach s) is
+// non-empty.  Also counts occupied strips and planes into the scalars.
+__global__ void __launch_bounds__(256)
+k_occupancy(int nb, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __restrict__ occ,
+            uint8_t* __restrict__ plane_occ, Scalars* __restrict__ sc) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t o = 0, po = 0;
+    if (b < nb) {
         const int k = b / g.S, sidx = b - k * g.S;
         int slo = ((sidx << g.log2H) - (g.support - 1)) >> g.log2H;
         if (slo < 0) slo = 0;
-        const uint8_t o = offsets[k * g.S + sidx + 1] > offsets[k * g.S + slo] ? 1 : 0;
-        occ[b] = o;
-        nocc += o;
+        o = offsets[(size_t)(k * g.S + sidx + 1) << kLogReplicas] >
+            offsets[(size_t)(k * g.S + slo) << kLogReplicas] ? 1u : 0u;
+        occ[b] = (uint8_t)o;
+        if (sidx == 0) {
+            po = offsets[(size_t)((k + 1) * g.S) << kLogReplicas] > offsets[(size_t)(k * g.S) << kLogReplicas] ? 1u : 0u;
+            plane_occ[k] = (uint8_t)po;
+        }
     }
-    __syncthreads();
-    part[t] = nocc;
-    __syncthreads();
-    for (int o = nt >> 1; o > 0; o >>= 1) {
-        if (t < o) part[t] += part[t + o];
-        __syncthreads();
+    o = wave_reduce_sum(o);
+    po = wave_reduce_sum(po);
+    if ((threadIdx.x & 63) == 0) {
+        if (o) atomicAdd(&sc->n_occ, (unsigned long long)o);
+        if (po) atomicAdd(&sc->n_planes, (unsigned long long)po);
     }
-    if (t == 0) sc->n_occ = part[0];
-    uint32_t npl = 0;
-    for (int k = t; k < g.nw; k += nt) {
-        const uint8_t o = offsets[(k + 1) * g.S] > offsets[k * g.S] ? 1 : 0;
-        plane_occ[k] = o;
-        npl += o;
-    }
-    __syncthreads();
-    part[t] = npl;
-    __syncthreads();
-    for (int o = nt >> 1; o > 0; o >>= 1) {
-        if (t < o) part[t] += part[t + o];
-        __syncthreads();
-    }
-    if (t == 0) sc->n_planes = part[0];
 }
 
 template <typename R, typename WT>
@@ -248,7 +301,7 @@ k_scatter(int64_t M, const double* __restrict__ uvw, const typename Cx<R>::T* __
     if (kk == 0xFFFFFFFFu) return;
     const double wt = (double)wts[m];
     RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
-    const uint32_t pos = offsets[kk] + rank[m];
+    const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + row_replica(m)] + rank[m];
     const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
     rec_cell[pos] = (uint32_t)q0 | ((uint32_t)p0 << 16);
     rec_frac[pos] = cmake<C>((R)(rg.x - rg.cx), (R)(rg.y - rg.cy));
@@ -306,8 +359,8 @@ k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double2* acc = reinterpret_cast<double2*>(smem_raw);
     C* lds = reinterpret_cast<C*>(smem_raw);
-    const int nblk = g.nw * g.S;
-    const int logical = xcd_remap(blockIdx.x, nblk);
+    // consecutive strips (and so the hot centre of the uv-plane) go round-robin over the XCDs
+    const int logical = blockIdx.x;
     const int k = logical / g.S, s = logical - k * g.S;
     const int tid = threadIdx.x;
     const int row0 = s * H;
@@ -326,7 +379,8 @@ k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
     if (s_lo < 0) s_lo = 0;
     constexpr int shift = FFT ? (n >> 1) : 0;   // place cell q at (q + n/2) mod n: the centring
     for (int sp = s_lo; sp <= s; ++sp) {
-        const uint32_t beg = offsets[k * g.S + sp], end = offsets[k * g.S + sp + 1];
+        const uint32_t beg = offsets[(size_t)(k * g.S + sp) << kLogReplicas];
+        const uint32_t end = offsets[(size_t)(k * g.S + sp + 1) << kLogReplicas];
         for (uint32_t r = beg + tid; r < end; r += NT) {
             const uint32_t cell = rec_cell[r];
             const int q0 = (int)(cell & 0xFFFFu), p0 = (int)(cell >> 16);

@@ -56,7 +56,7 @@ struct wsimg_plan {
     // device memory
     Partial* partials = nullptr;
     Scalars* scalars = nullptr;
-    uint32_t *counts = nullptr, *offsets = nullptr;
+    uint32_t *counts = nullptr, *offsets = nullptr, *tile_sums = nullptr;
     uint8_t *occ = nullptr, *plane_occ = nullptr;
     uint32_t *key = nullptr, *rank = nullptr, *rec_cell = nullptr;
     void *rec_frac = nullptr, *rec_vis = nullptr, *inter = nullptr;
@@ -271,8 +271,9 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, c
     const Geom g = pl->g;
     hipStream_t s = pl->stream;
     const int64_t nbk = pl->nb;
-    hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(blocks_for(nbk, 256), 4096)), dim3(256), 0, s,
-                       pl->counts, nbk, 0u);
+    const int64_t ncnt = nbk * kReplicas;
+    hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(blocks_for(ncnt, 256), 8192)), dim3(256), 0, s,
+                       pl->counts, ncnt, 0u);
     WS_LAUNCH_CHECK("fill");
     if (auto r = st.after(0)) return r;
 
@@ -294,9 +295,16 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, c
     }
     if (auto r = st.after(2)) return r;
 
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (int)nbk, pl->counts, pl->offsets, g, pl->occ,
-                       pl->plane_occ, pl->scalars);
-    WS_LAUNCH_CHECK("scan");
+    const int ntiles = (int)((ncnt + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, ncnt, pl->counts, pl->tile_sums);
+    WS_LAUNCH_CHECK("scan_tiles");
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ntiles, pl->tile_sums);
+    WS_LAUNCH_CHECK("scan_top");
+    hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(256), 0, s, ncnt, pl->counts, pl->tile_sums, pl->offsets);
+    WS_LAUNCH_CHECK("scan_down");
+    hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nbk, 256)), dim3(256), 0, s, (int)nbk, pl->offsets, g,
+                       pl->occ, pl->plane_occ, pl->scalars);
+    WS_LAUNCH_CHECK("occupancy");
     if (auto r = st.after(3)) return r;
 
     if (M > 0) {
@@ -312,7 +320,6 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, c
 template <typename R>
 wsimg_status run_image(wsimg_plan* pl, int64_t M, const double* uvw, const void* vis, const void* wts,
                        double freq, void* image, bool grid_only) {
-    using C = typename Cx<R>::T;
     Stamp st(pl);
     if (auto r = st.begin()) return r;
     if (auto r = run_sort<R>(pl, st, M, uvw, vis, wts, freq)) return r;
@@ -422,8 +429,9 @@ wsimg_status wsimg_plan_create(wsimg_plan** out, const wsimg_params* p, int64_t 
     if (!r) { r = dev_alloc(pl, &tmp, (bytes), name); pl->field = (decltype(pl->field))tmp; }
     ALLOC(partials, sizeof(Partial) * pl->nparts, "partials");
     ALLOC(scalars, sizeof(Scalars), "scalars");
-    ALLOC(counts, sizeof(uint32_t) * pl->nb, "counts");
-    ALLOC(offsets, sizeof(uint32_t) * (pl->nb + 1), "offsets");
+    ALLOC(counts, sizeof(uint32_t) * pl->nb * kReplicas, "counts");
+    ALLOC(offsets, sizeof(uint32_t) * (pl->nb * kReplicas + 1), "offsets");
+    ALLOC(tile_sums, sizeof(uint32_t) * ((pl->nb * kReplicas + kScanTile - 1) / kScanTile), "scan tiles");
     ALLOC(occ, (size_t)pl->nb, "occupancy");
     ALLOC(plane_occ, (size_t)g.nw, "plane occupancy");
     ALLOC(key, sizeof(uint32_t) * mv, "keys");
