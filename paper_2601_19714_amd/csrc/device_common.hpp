@@ -73,33 +73,9 @@ __device__ __forceinline__ int plane_index(double w, double w_lo, double dw, int
     return (int)kf;
 }
 
-// sin(2 pi t) and cos(2 pi t) for |t| <= 1/2 (t in turns).  Quadrant reduction
-// q = rint(4t), r = t - q/4 (exact), |r| <= 1/8; then the Taylor series of sin and cos
-// of 2 pi r (error below 2e-9 in float, 5e-16 in double), and the quadrant rotation.
-__device__ __forceinline__ void sincos_turn(float t, float* s, float* c) {
-    const float q = rintf(4.0f * t);
-    const float r = t - 0.25f * q;
-    const float r2 = r * r;
-    float ps = -15.0946425768229903918f;
-    ps = ps * r2 + 42.058693944897653145f;
-    ps = ps * r2 + -76.7058597530613858416f;
-    ps = ps * r2 + 81.6052492760750542034f;
-    ps = ps * r2 + -41.341702240399760234f;
-    ps = ps * r2 + 6.28318530717958647693f;
-    const float sr = ps * r;
-    float pc = 7.90353637131846880421f;
-    pc = pc * r2 + -26.4262567833743974529f;
-    pc = pc * r2 + 60.2446413718766603627f;
-    pc = pc * r2 + -85.456817206693727736f;
-    pc = pc * r2 + 64.939394022668291491f;
-    pc = pc * r2 + -19.7392088021787172377f;
-    const float cr = pc * r2 + 1.0f;
-    const int qi = ((int)q) & 3;
-    const float ss = (qi & 1) ? cr : sr, cc = (qi & 1) ? sr : cr;
-    *s = (qi & 2) ? -ss : ss;
-    *c = ((qi + 1) & 2) ? -cc : cc;
-}
-
+// sin(2 pi t) and cos(2 pi t) for |t| <= 1/2 (t in turns), float64.  Quadrant reduction
+// q = rint(4t), r = t - q/4 (exact), |r| <= 1/8; then the Taylor series of sin and cos of
+// 2 pi r to degree 21 / 22 (truncation below 5e-16) and the quadrant rotation.
 __device__ __forceinline__ void sincos_turn(double t, double* s, double* c) {
     const double q = rint(4.0 * t);
     const double r = t - 0.25 * q;

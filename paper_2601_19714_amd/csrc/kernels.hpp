@@ -38,6 +38,8 @@ struct Geom {
 struct Scalars {
     double w_lo, w_hi, dw, sum_w;
     unsigned long long n_kept, n_in, n_occ, n_planes;
+    // work list of occupied strips: heavy ones from the front, light ones from the back
+    unsigned int n_heavy, n_light, work_next, pad;
 };
 
 struct Partial {
@@ -153,36 +155,64 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, int64_t M, Scal
         r.n_in = (unsigned long long)M;
         r.n_occ = 0;
         r.n_planes = 0;
+        r.n_heavy = 0;
+        r.n_light = 0;
+        r.work_next = 0;
+        r.pad = 0;
         *sc = r;
     }
 }
 
 // Bucket counters are replicated kReplicas times, laid out [bucket][replica]; row m counts
-// in replica (m >> 8) mod kReplicas.  The rows of one hot bucket (tens of thousands near the
+// in replica (m / 256) mod kReplicas.  (Blocks of consecutive rows, not single rows: a
+// bucket's records keep their time-major order, so the lanes of a gridding wave hold
+// different baselines and rarely hit the same cell.)  The rows of one hot bucket (tens of thousands near the
 // uv-plane centre) then spread their atomics over kReplicas addresses instead of one, and
 // the bucket's rows still end up contiguous after the scan.
 constexpr int kReplicas = 64;
 constexpr int kLogReplicas = 6;
 __device__ __forceinline__ uint32_t row_replica(int64_t m) { return (uint32_t)(m >> 8) & (kReplicas - 1); }
 
+// Ranks are taken once per distinct key in a wave: the lanes sharing a key elect a leader,
+// which adds their count to the counter; each lane's rank is the returned base plus the
+// number of lower lanes with the same key.
 template <typename WT>
 __global__ void __launch_bounds__(256)
 k_key(int64_t M, const double* __restrict__ uvw, const WT* __restrict__ wts, double freq, Geom g,
       const Scalars* __restrict__ sc, uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
       uint32_t* __restrict__ counts) {
     const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const double wt = (double)wts[m];
-    RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
-    uint32_t kk = 0xFFFFFFFFu, rr = 0;
-    if (rg.keep) {
-        const int k = plane_index(rg.w, sc->w_lo, sc->dw, g.nw);
-        const int p0 = (int)rg.cy - g.half;
-        kk = (uint32_t)(k * g.S + (p0 >> g.log2H));
-        rr = atomicAdd(&counts[((size_t)kk << kLogReplicas) + row_replica(m)], 1u);
+    const bool in = m < M;
+    uint32_t kk = 0xFFFFFFFFu;
+    if (in) {
+        const double wt = (double)wts[m];
+        RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
+        if (rg.keep) {
+            const int k = plane_index(rg.w, sc->w_lo, sc->dw, g.nw);
+            const int p0 = (int)rg.cy - g.half;
+            kk = (uint32_t)(k * g.S + (p0 >> g.log2H));
+        }
     }
-    key[m] = kk;
-    rank[m] = rr;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // all lanes of a block share the replica (m / 256 is uniform in a 256-thread block)
+    const uint32_t rep = row_replica((int64_t)blockIdx.x * blockDim.x);
+    unsigned long long todo = __ballot(kk != 0xFFFFFFFFu);
+    uint32_t rr = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t lkey = __shfl(kk, leader, 64);
+        const unsigned long long same = __ballot(kk == lkey);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counts[((size_t)lkey << kLogReplicas) + rep], (uint32_t)__popcll(same));
+        base = __shfl(base, leader, 64);
+        if (kk == lkey) rr = base + (uint32_t)__popcll(same & below);
+        todo &= ~same;
+    }
+    if (in) {
+        key[m] = kk;
+        rank[m] = rr;
+    }
 }
 
 // Exclusive scan of the replicated counters (total = nb * kReplicas entries) in three
@@ -261,27 +291,47 @@ k_scan_down(int64_t total, const uint32_t* __restrict__ counts, const uint32_t* 
 
 // Strip and plane occupancy.  occ[k*S + s] = 1 when some record of plane k has a tap row
 // inside strip s, i.e. one of the buckets s_lo(s)..s (the strips whose rows can reach s) is
-// non-empty.  Also counts occupied strips and planes into the scalars.
+// non-empty.  Occupied strips also go to the gridding work list: strips with more than
+// kHeavyStrip record visits from the front (list[0..n_heavy)), the rest from the back
+// (list[nb - n_light .. nb)), so the long ones start first.  Counts go to the scalars.
+constexpr uint32_t kHeavyStrip = 4096;
+
 __global__ void __launch_bounds__(256)
 k_occupancy(int nb, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __restrict__ occ,
-            uint8_t* __restrict__ plane_occ, Scalars* __restrict__ sc) {
+            uint8_t* __restrict__ plane_occ, uint32_t* __restrict__ list, Scalars* __restrict__ sc) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t o = 0, po = 0;
+    uint32_t o = 0, po = 0, visits = 0;
     if (b < nb) {
         const int k = b / g.S, sidx = b - k * g.S;
         int slo = ((sidx << g.log2H) - (g.support - 1)) >> g.log2H;
         if (slo < 0) slo = 0;
-        o = offsets[(size_t)(k * g.S + sidx + 1) << kLogReplicas] >
-            offsets[(size_t)(k * g.S + slo) << kLogReplicas] ? 1u : 0u;
+        visits = offsets[(size_t)(k * g.S + sidx + 1) << kLogReplicas] -
+                 offsets[(size_t)(k * g.S + slo) << kLogReplicas];
+        o = visits > 0 ? 1u : 0u;
         occ[b] = (uint8_t)o;
         if (sidx == 0) {
             po = offsets[(size_t)((k + 1) * g.S) << kLogReplicas] > offsets[(size_t)(k * g.S) << kLogReplicas] ? 1u : 0u;
             plane_occ[k] = (uint8_t)po;
         }
     }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long heavy = __ballot(o && visits > kHeavyStrip);
+    const unsigned long long light = __ballot(o && visits <= kHeavyStrip);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t hbase = 0, lbase = 0;
+    if (lane == 0) {
+        if (heavy) hbase = atomicAdd(&sc->n_heavy, (unsigned)__popcll(heavy));
+        if (light) lbase = atomicAdd(&sc->n_light, (unsigned)__popcll(light));
+    }
+    hbase = __shfl(hbase, 0, 64);
+    lbase = __shfl(lbase, 0, 64);
+    if (o) {
+        if (visits > kHeavyStrip) list[hbase + __popcll(heavy & below)] = (uint32_t)b;
+        else list[nb - 1 - (lbase + __popcll(light & below))] = (uint32_t)b;
+    }
     o = wave_reduce_sum(o);
     po = wave_reduce_sum(po);
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         if (o) atomicAdd(&sc->n_occ, (unsigned long long)o);
         if (po) atomicAdd(&sc->n_planes, (unsigned long long)po);
     }
@@ -345,32 +395,24 @@ template <typename R, int LOG2N> struct Shape {
 // 2500 for W = 7), and float32 atomic accumulation alone costs ~1e-5 of the image there.
 // The per-tap products are formed in the plan's precision; the float path converts the
 // strip to float32 in place before its FFT.
+// One occupied strip (plane k, strip s) by the whole work-group.
 template <typename R, bool FFT, int LOG2N>
-__global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
-k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restrict__ occ,
-            const uint32_t* __restrict__ rec_cell, const typename Cx<R>::T* __restrict__ rec_frac,
-            const typename Cx<R>::T* __restrict__ rec_vis, const R* __restrict__ kbc,
-            const typename Cx<R>::T* __restrict__ tw, typename Cx<R>::T* __restrict__ out) {
+__device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned char* smem_raw,
+                                           const uint32_t* __restrict__ offsets,
+                                           const uint32_t* __restrict__ rec_cell,
+                                           const typename Cx<R>::T* __restrict__ rec_frac,
+                                           const typename Cx<R>::T* __restrict__ rec_vis,
+                                           const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
+                                           typename Cx<R>::T* __restrict__ out) {
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
     constexpr int n = SH::N, H = SH::H, NT = SH::NT1, nmask = n - 1;
     constexpr int LOG2H = Log2Of<H>::value_any;
     constexpr int elems = H * n;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     double2* acc = reinterpret_cast<double2*>(smem_raw);
     C* lds = reinterpret_cast<C*>(smem_raw);
-    // consecutive strips (and so the hot centre of the uv-plane) go round-robin over the XCDs
-    const int logical = blockIdx.x;
-    const int k = logical / g.S, s = logical - k * g.S;
     const int tid = threadIdx.x;
     const int row0 = s * H;
-    if (!occ[logical]) {
-        if constexpr (!FFT) {
-            C* dst = out + ((size_t)k << (2 * LOG2N)) + ((size_t)row0 << LOG2N);
-            for (int e = tid; e < elems; e += NT) dst[e] = cmake<C>((R)0, (R)0);
-        }
-        return;
-    }
     for (int e = tid; e < SH::LDS1; e += NT) acc[e] = make_double2(0.0, 0.0);
     __syncthreads();
 
@@ -450,6 +492,56 @@ k_grid_rows(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
             const double2 a = acc[lds_pad(e)];
             dst[e] = cmake<C>((R)a.x, (R)a.y);
         }
+    }
+}
+
+// The gridding step alone: one work-group per strip of every plane; empty strips are zeroed.
+template <typename R, int LOG2N>
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
+k_grid_only(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restrict__ occ,
+            const uint32_t* __restrict__ rec_cell, const typename Cx<R>::T* __restrict__ rec_frac,
+            const typename Cx<R>::T* __restrict__ rec_vis, const R* __restrict__ kbc,
+            typename Cx<R>::T* __restrict__ out) {
+    using C = typename Cx<R>::T;
+    using SH = Shape<R, LOG2N>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int b = blockIdx.x;
+    const int k = b / g.S, s = b - k * g.S;
+    if (!occ[b]) {
+        C* dst = out + ((size_t)k << (2 * LOG2N)) + ((size_t)(s * SH::H) << LOG2N);
+        for (int e = threadIdx.x; e < SH::H * SH::N; e += SH::NT1) dst[e] = cmake<C>((R)0, (R)0);
+        return;
+    }
+    grid_strip<R, false, LOG2N>(g, k, s, smem_raw, offsets, rec_cell, rec_frac, rec_vis, kbc, nullptr, out);
+}
+
+// Gridding + row FFT: a persistent grid walks the work list of occupied strips (heavy ones
+// first) through an atomic counter; every work-group leaves once the list is exhausted.
+template <typename R, int LOG2N>
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
+k_grid_rows(Geom g, int nb, Scalars* __restrict__ sc, const uint32_t* __restrict__ list,
+            const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
+            const typename Cx<R>::T* __restrict__ rec_frac, const typename Cx<R>::T* __restrict__ rec_vis,
+            const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
+            typename Cx<R>::T* __restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int item;
+    const unsigned n_heavy = sc->n_heavy, n_light = sc->n_light;
+    while (true) {
+        if (threadIdx.x == 0) {
+            const unsigned i = atomicAdd(&sc->work_next, 1u);
+            int b = -1;
+            if (i < n_heavy) b = (int)list[i];
+            else if (i - n_heavy < n_light) b = (int)list[nb - 1 - (int)(i - n_heavy)];
+            item = b;
+        }
+        __syncthreads();
+        const int b = item;
+        __syncthreads();
+        if (b < 0) break;
+        const int k = b / g.S, s = b - k * g.S;
+        grid_strip<R, true, LOG2N>(g, k, s, smem_raw, offsets, rec_cell, rec_frac, rec_vis, kbc, tw, out);
+        __syncthreads();
     }
 }
 
@@ -567,7 +659,14 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
             double cyc = wk * (SH::NM1_LDS ? nm1s[s * NT + tid] : nm1r[SH::NM1_LDS ? 0 : s]);
             cyc -= rint(cyc);
             R sn, cs;
-            sincos_turn((R)cyc, &sn, &cs);
+            if constexpr (sizeof(R) == 4) {
+                // hardware sin/cos of 2 pi t, t in turns (|t| <= 1/2): 1.3e-7 absolute error
+                const float t = (float)cyc;
+                sn = __builtin_amdgcn_sinf(t);
+                cs = __builtin_amdgcn_cosf(t);
+            } else {
+                sincos_turn(cyc, &sn, &cs);
+            }
             const R val = x[s].x * cs - x[s].y * sn;
             if constexpr (sizeof(R) == 4) {
                 const R y = val - comp[s];

@@ -58,6 +58,8 @@ struct wsimg_plan {
     Scalars* scalars = nullptr;
     uint32_t *counts = nullptr, *offsets = nullptr, *tile_sums = nullptr;
     uint8_t *occ = nullptr, *plane_occ = nullptr;
+    uint32_t* list = nullptr;      // work list of occupied strips
+    int persist_blocks = 256;      // work-groups of the persistent gridding kernel
     uint32_t *key = nullptr, *rank = nullptr, *rec_cell = nullptr;
     void *rec_frac = nullptr, *rec_vis = nullptr, *inter = nullptr;
     void *tw = nullptr, *inv_taper = nullptr, *kbc = nullptr;
@@ -159,9 +161,9 @@ wsimg_status configure_shape(wsimg_plan* pl) {
     pl->nt2 = SH::NT2;
     pl->lds1 = SH::LDS1_BYTES;
     pl->lds2 = SH::LDS2_BYTES;
-    WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, true, LOG2N>,
+    WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
-    WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, false, LOG2N>,
+    WS_HIP(hipFuncSetAttribute((const void*)k_grid_only<R, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
@@ -178,15 +180,16 @@ template <typename R, int LOG2N>
 wsimg_status launch_grid_rows(wsimg_plan* pl, bool fft, void* out) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
-    const unsigned nblk = (unsigned)(g.nw * g.S);
-    if (fft)
-        hipLaunchKernelGGL((k_grid_rows<R, true, LOG2N>), dim3(nblk), dim3(pl->nt1), pl->lds1, pl->stream, g,
-                           pl->offsets, pl->occ, pl->rec_cell, (const C*)pl->rec_frac, (const C*)pl->rec_vis,
-                           (const R*)pl->kbc, (const C*)pl->tw, (C*)out);
-    else
-        hipLaunchKernelGGL((k_grid_rows<R, false, LOG2N>), dim3(nblk), dim3(pl->nt1), pl->lds1, pl->stream, g,
-                           pl->offsets, pl->occ, pl->rec_cell, (const C*)pl->rec_frac, (const C*)pl->rec_vis,
-                           (const R*)pl->kbc, (const C*)pl->tw, (C*)out);
+    if (fft) {
+        hipLaunchKernelGGL((k_grid_rows<R, LOG2N>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1), pl->lds1,
+                           pl->stream, g, (int)pl->nb, pl->scalars, pl->list, pl->offsets, pl->rec_cell,
+                           (const C*)pl->rec_frac, (const C*)pl->rec_vis, (const R*)pl->kbc, (const C*)pl->tw,
+                           (C*)out);
+    } else {
+        hipLaunchKernelGGL((k_grid_only<R, LOG2N>), dim3((unsigned)(g.nw * g.S)), dim3(pl->nt1), pl->lds1,
+                           pl->stream, g, pl->offsets, pl->occ, pl->rec_cell, (const C*)pl->rec_frac,
+                           (const C*)pl->rec_vis, (const R*)pl->kbc, (C*)out);
+    }
     WS_LAUNCH_CHECK("grid_rows");
     return WSIMG_OK;
 }
@@ -303,7 +306,7 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, c
     hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(256), 0, s, ncnt, pl->counts, pl->tile_sums, pl->offsets);
     WS_LAUNCH_CHECK("scan_down");
     hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nbk, 256)), dim3(256), 0, s, (int)nbk, pl->offsets, g,
-                       pl->occ, pl->plane_occ, pl->scalars);
+                       pl->occ, pl->plane_occ, pl->list, pl->scalars);
     WS_LAUNCH_CHECK("occupancy");
     if (auto r = st.after(3)) return r;
 
@@ -420,6 +423,11 @@ wsimg_status wsimg_plan_create(wsimg_plan** out, const wsimg_params* p, int64_t 
 
     hipError_t he = hipGetDevice(&pl->device);
     if (he != hipSuccess) { delete pl; return fail(WSIMG_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he)); }
+    int cus = 0;
+    he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device);
+    if (he != hipSuccess || cus <= 0) { delete pl; return fail(WSIMG_E_HIP, "hipDeviceGetAttribute(CU count) failed"); }
+    // as many strip work-groups as fit at once: one per CU while the LDS strip exceeds 80 KB
+    pl->persist_blocks = cus * std::max(1, (int)((160 * 1024) / std::max<size_t>(pl->lds1, 1)));
 
     wsimg_status r = WSIMG_OK;
     const size_t mv = (size_t)std::max<int64_t>(max_vis, 1);
@@ -433,6 +441,7 @@ wsimg_status wsimg_plan_create(wsimg_plan** out, const wsimg_params* p, int64_t 
     ALLOC(offsets, sizeof(uint32_t) * (pl->nb * kReplicas + 1), "offsets");
     ALLOC(tile_sums, sizeof(uint32_t) * ((pl->nb * kReplicas + kScanTile - 1) / kScanTile), "scan tiles");
     ALLOC(occ, (size_t)pl->nb, "occupancy");
+    ALLOC(list, sizeof(uint32_t) * (size_t)pl->nb, "strip work list");
     ALLOC(plane_occ, (size_t)g.nw, "plane occupancy");
     ALLOC(key, sizeof(uint32_t) * mv, "keys");
     ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
