@@ -30,6 +30,15 @@ template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s)
 // LDS element index with one pad slot per 16 elements: keeps the strided Stockham
 // writes and the 16-wide butterfly reads off common banks.
 __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
+// Hide a (wave-uniform) pointer's value from the optimiser.  Used on the twiddle table at
+// the top of loops over strips or planes, so its loads stay inside each FFT pass instead of
+// being hoisted out of the loop into registers the passes need.
+template <typename T>
+__device__ __forceinline__ const T* opaque_ptr(const T* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 __host__ __device__ __forceinline__ int lds_padded_elems(int e) { return e + (e >> 4) + 1; }
 // padded element count rounded up to an even number, so a double array can follow it
 constexpr int lds_padded_elems_c(int e) { return (e + (e >> 4) + 2) & ~1; }

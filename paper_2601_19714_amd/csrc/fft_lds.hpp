@@ -5,9 +5,10 @@
 // element index passed through lds_pad).  Stockham autosort: each pass reads R inputs
 // a stride N/R apart, twiddles them, runs an R-point DFT in registers and writes the R
 // outputs a stride L apart, so the result ends in natural order with no bit reversal.
-// Pass layout: radix 16 first, then one radix-2/4/8 pass when LOG2N is not a multiple of
-// 4, then radix 16.  Twiddles come from a table tw[t] = exp(+2 pi i t / N) built in
-// float64 on the host.  Every pass is written for NT threads with NT * 16 >= ROWS * N.
+// Pass layout on a base radix R (8 here): radix R first, then one smaller-radix pass when
+// LOG2N is not a multiple of log2 R, then radix R.  Twiddles come from a table
+// tw[t] = exp(+2 pi i t / N) built in float64 on the host.  Every pass is written for NT
+// threads with NT * R >= ROWS * N.
 #pragma once
 
 #include "device_common.hpp"
@@ -86,16 +87,18 @@ template <int V> struct Log2Of {
 };
 template <> struct Log2Of<1> { static constexpr int value = 0; static constexpr int value_any = 0; };
 
-// Pass layout of an N = 2^LOG2N transform (LOG2N >= 4).
-template <int LOG2N> struct FftPlan {
-    static constexpr int REM = LOG2N & 3;
-    // radix (log2) of the last pass; the only pass when LOG2N == 4
-    static constexpr int LAST_LOG = LOG2N <= 4 ? LOG2N : ((LOG2N < 8 && REM) ? REM : 4);
+// Pass layout of an N = 2^LOG2N transform on a base radix R = 2^LOGR (R elements per thread):
+// [R (first)] [one radix-2^(LOG2N mod LOGR) pass when LOG2N is not a multiple of LOGR] [R ...].
+template <int LOG2N, int LOGR> struct FftPlan {
+    static constexpr int REM = LOG2N % LOGR;
+    // radix (log2) of the last pass; the only pass when LOG2N <= LOGR
+    static constexpr int LAST_LOG = LOG2N <= LOGR ? LOG2N : ((LOG2N < 2 * LOGR && REM) ? REM : LOGR);
     // log2 L at which the last pass starts
     static constexpr int LAST_L = LOG2N - LAST_LOG;
 };
 
-// One Stockham pass (LDS to LDS) at sub-length L = 2^LOG2L.
+// One Stockham pass (LDS to LDS) at sub-length L = 2^LOG2L, for NT threads holding E elements
+// each (E = 8 or 16; a radix-RAD pass gives each thread E / RAD butterflies).
 template <int RAD, int LOG2N, int LOG2L, int ROWS, int NT, typename C>
 __device__ __forceinline__ void stockham_pass(C* lds, const C* __restrict__ tw) {
     constexpr int LOGR = Log2Of<RAD>::value;
@@ -136,36 +139,36 @@ __device__ __forceinline__ void stockham_pass(C* lds, const C* __restrict__ tw) 
     __syncthreads();
 }
 
-// Passes from sub-length 2^LOG2L up to (not including) 2^STOP, in the plan's layout:
-// the radix-2/4/8 pass (if any) sits at LOG2L == 4, right after the first radix-16 pass.
-template <int LOG2N, int LOG2L, int STOP, int ROWS, int NT, typename C>
+// Passes from sub-length 2^LOG2L up to (not including) 2^STOP in the plan's layout: the
+// odd-radix pass (if any) sits at LOG2L == LOGR, right after the first pass.
+template <int LOG2N, int LOGR, int LOG2L, int STOP, int ROWS, int NT, typename C>
 __device__ __forceinline__ void stockham_range(C* lds, const C* __restrict__ tw) {
     if constexpr (LOG2L < STOP) {
-        constexpr int REM = LOG2N & 3;
-        constexpr int LOGR = (REM != 0 && LOG2L == 4) ? REM : 4;
-        stockham_pass<(1 << LOGR), LOG2N, LOG2L, ROWS, NT>(lds, tw);
-        stockham_range<LOG2N, LOG2L + LOGR, STOP, ROWS, NT>(lds, tw);
+        constexpr int REM = LOG2N % LOGR;
+        constexpr int LR = (REM != 0 && LOG2L == LOGR) ? REM : LOGR;
+        stockham_pass<(1 << LR), LOG2N, LOG2L, ROWS, NT>(lds, tw);
+        stockham_range<LOG2N, LOGR, LOG2L + LR, STOP, ROWS, NT>(lds, tw);
     }
 }
 
-// Full in-place transform of ROWS rows held in LDS (LOG2N >= 4).
-template <int LOG2N, int ROWS, int NT, typename C>
+// Full in-place transform of ROWS rows held in LDS (LOG2N > LOGR).
+template <int LOG2N, int LOGR, int ROWS, int NT, typename C>
 __device__ __forceinline__ void fft_rows_lds(C* lds, const C* __restrict__ tw) {
-    static_assert(LOG2N >= 4, "transforms start with a radix-16 pass");
-    stockham_pass<16, LOG2N, 0, ROWS, NT>(lds, tw);
-    stockham_range<LOG2N, 4, LOG2N, ROWS, NT>(lds, tw);
+    static_assert(LOG2N > LOGR, "transforms start with a full-radix pass");
+    stockham_pass<(1 << LOGR), LOG2N, 0, ROWS, NT>(lds, tw);
+    stockham_range<LOG2N, LOGR, LOGR, LOG2N, ROWS, NT>(lds, tw);
 }
 
-// Last pass (L * RAD == N) from LDS into registers.  out[t * RAD + m] holds output bin
-// b + m * (N / RAD) of row (g >> LSUB), g = threadIdx.x + t * NT, b = g mod (N / RAD);
-// slots of inactive threads are zero.  No barrier at the end.
-template <int LOG2N, int ROWS, int NT, typename C>
+// Last pass (L * RAD == N) from LDS into registers.  out[t * RAD + m] (E = 2^LOGR slots)
+// holds output bin b + m * (N / RAD) of row (g >> LSUB), g = threadIdx.x + t * NT,
+// b = g mod (N / RAD); slots of inactive threads are zero.  No barrier at the end.
+template <int LOG2N, int LOGR, int ROWS, int NT, typename C>
 __device__ __forceinline__ void fft_last_to_regs(const C* lds, const C* __restrict__ tw, C* out) {
-    constexpr int LOGR = FftPlan<LOG2N>::LAST_LOG;
-    constexpr int RAD = 1 << LOGR;
-    constexpr int LSUB = LOG2N - LOGR;
+    constexpr int LLOG = FftPlan<LOG2N, LOGR>::LAST_LOG;
+    constexpr int RAD = 1 << LLOG;
+    constexpr int LSUB = LOG2N - LLOG;
     constexpr int NBF = ROWS << LSUB;
-    constexpr int BPT = 16 / RAD;
+    constexpr int BPT = (1 << LOGR) / RAD;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int t = 0; t < BPT; ++t) {
@@ -188,13 +191,13 @@ __device__ __forceinline__ void fft_last_to_regs(const C* lds, const C* __restri
     }
 }
 
-// Row (column of the image block) c and bin i' held by register slot s (0..15) of thread
-// tid after fft_last_to_regs.
-template <int LOG2N, int ROWS, int NT>
+// Row (image column of the block) c and bin i' held by register slot s of thread tid after
+// fft_last_to_regs.
+template <int LOG2N, int LOGR, int ROWS, int NT>
 __device__ __forceinline__ bool last_slot(int tid, int s, int& c, int& ip) {
-    constexpr int LOGR = FftPlan<LOG2N>::LAST_LOG;
-    constexpr int LSUB = LOG2N - LOGR;
-    const int t = s >> LOGR, m = s & ((1 << LOGR) - 1);
+    constexpr int LLOG = FftPlan<LOG2N, LOGR>::LAST_LOG;
+    constexpr int LSUB = LOG2N - LLOG;
+    const int t = s >> LLOG, m = s & ((1 << LLOG) - 1);
     const int g = tid + t * NT;
     if (g >= (ROWS << LSUB)) return false;
     c = g >> LSUB;

@@ -337,13 +337,26 @@ k_occupancy(int nb, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __res
     }
 }
 
+// Sorted records.  float: one 16-byte record per row,
+//   x: q0 (13 bits) | p0 mod H (5 bits) | low 14 bits of the x offset code,
+//   y: high 9 bits of the x offset code | y offset code (23 bits),
+//   z, w: W*V as float2,
+// where an offset f = x - floor(x + 1/2) in [-1/2, 1/2) is coded as round((f + 1/2) 2^23)
+// (a resolution of 1.2e-7 cells; the tap weights change by at most ~6e-8 of their peak).
+// double: rec_cell (q0 | p0 << 16) plus two double2 per row: the offsets, then W*V.
+constexpr double kFracScale = 8388608.0;   // 2^23
+
+__device__ __forceinline__ uint32_t frac_code(double f) {
+    int c = __double2int_rn((f + 0.5) * kFracScale);
+    return (uint32_t)(c < 0 ? 0 : (c > 8388607 ? 8388607 : c));
+}
+
 template <typename R, typename WT>
 __global__ void __launch_bounds__(256)
 k_scatter(int64_t M, const double* __restrict__ uvw, const typename Cx<R>::T* __restrict__ vis,
           const WT* __restrict__ wts, double freq, Geom g, const uint32_t* __restrict__ key,
           const uint32_t* __restrict__ rank, const uint32_t* __restrict__ offsets,
-          uint32_t* __restrict__ rec_cell, typename Cx<R>::T* __restrict__ rec_frac,
-          typename Cx<R>::T* __restrict__ rec_vis) {
+          uint32_t* __restrict__ rec_cell, void* __restrict__ rec) {
     using C = typename Cx<R>::T;
     const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (m >= M) return;
@@ -353,38 +366,78 @@ k_scatter(int64_t M, const double* __restrict__ uvw, const typename Cx<R>::T* __
     RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
     const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + row_replica(m)] + rank[m];
     const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
-    rec_cell[pos] = (uint32_t)q0 | ((uint32_t)p0 << 16);
-    rec_frac[pos] = cmake<C>((R)(rg.x - rg.cx), (R)(rg.y - rg.cy));
     const C v = vis[m];
     const R w = (R)wts[m];
-    rec_vis[pos] = cmake<C>(w * v.x, w * v.y);
+    if constexpr (sizeof(R) == 4) {
+        const uint32_t ux = frac_code(rg.x - rg.cx), uy = frac_code(rg.y - rg.cy);
+        const uint32_t pr = (uint32_t)p0 & (uint32_t)(g.H - 1);
+        uint4 q;
+        q.x = (uint32_t)q0 | (pr << 13) | ((ux & 0x3FFFu) << 18);
+        q.y = (ux >> 14) | (uy << 9);
+        q.z = __float_as_uint(w * v.x);
+        q.w = __float_as_uint(w * v.y);
+        reinterpret_cast<uint4*>(rec)[pos] = q;
+    } else {
+        rec_cell[pos] = (uint32_t)q0 | ((uint32_t)p0 << 16);
+        double2* r2 = reinterpret_cast<double2*>(rec);
+        r2[2 * (size_t)pos] = make_double2(rg.x - rg.cx, rg.y - rg.cy);
+        r2[2 * (size_t)pos + 1] = make_double2(w * v.x, w * v.y);
+    }
+}
+
+// One record: tap origin (q0, p0), sub-cell offsets and W*V in the plan precision.
+template <typename R>
+__device__ __forceinline__ void load_record(const uint32_t* __restrict__ rec_cell, const void* __restrict__ rec,
+                                            uint32_t r, int strip, int log2H, int& q0, int& p0,
+                                            typename Cx<R>::T& fr, typename Cx<R>::T& v) {
+    using C = typename Cx<R>::T;
+    if constexpr (sizeof(R) == 4) {
+        const uint4 q = reinterpret_cast<const uint4*>(rec)[r];
+        q0 = (int)(q.x & 0x1FFFu);
+        p0 = (strip << log2H) + (int)((q.x >> 13) & 0x1Fu);
+        const uint32_t ux = (q.x >> 18) | ((q.y & 0x1FFu) << 14), uy = q.y >> 9;
+        const float inv = 1.0f / 8388608.0f;
+        fr = cmake<C>((float)ux * inv - 0.5f, (float)uy * inv - 0.5f);
+        v = cmake<C>(__uint_as_float(q.z), __uint_as_float(q.w));
+    } else {
+        const uint32_t cell = rec_cell[r];
+        q0 = (int)(cell & 0xFFFFu);
+        p0 = (int)(cell >> 16);
+        const double2* r2 = reinterpret_cast<const double2*>(rec);
+        fr = r2[2 * (size_t)r];
+        v = r2[2 * (size_t)r + 1];
+    }
 }
 
 // ---------------------------------------------------------------------------------------
-// Work-group shapes, fixed per (precision, image size).
+// Work-group shapes, fixed per (precision, image size).  The FFTs run on a radix-8 base with
+// 8 elements per thread, so a 1024-thread work-group holds 8192 points in registers between
+// LDS exchanges and a CU keeps 16 waves (4 per SIMD) in flight at <= 128 VGPRs.
 //   pass 1: H grid rows per strip; the strip accumulates in float64 (16 B per cell) whatever
-//           the precision, so H * N <= 8192 cells; NT1 = H * N / 16 threads (one radix-16
-//           butterfly each per pass);
+//           the precision, so H * N <= 8192 cells; NT1 = H * N / 8 threads;
 //   pass 2: B image columns per block, B * N = 8192 (float) / 4096 (double) pixels,
-//           NT2 = B * N / 16 threads (16 output pixels each).
+//           NT2 = B * N / 8 threads (8 output pixels each).
+constexpr int kLogRadix = 3;
+constexpr int kElems = 1 << kLogRadix;      // elements per thread in every FFT pass
+
 template <typename R, int LOG2N> struct Shape {
     static constexpr int N = 1 << LOG2N;
     static constexpr int CAP1 = 8192;
     static constexpr int H0 = CAP1 / N < 32 ? CAP1 / N : 32;
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
-    static constexpr int NT1 = (H * N / 16) < 64 ? 64 : (H * N / 16);
+    static constexpr int NT1 = (H * N / kElems) < 64 ? 64 : (H * N / kElems);
     static constexpr int PX2 = sizeof(R) == 4 ? 8192 : 4096;
     static constexpr int B0 = PX2 / N < N ? PX2 / N : N;
     static constexpr int B = B0 < 1 ? 1 : B0;
-    static constexpr int NT2 = (B * N / 16) < 64 ? 64 : (B * N / 16);
+    static constexpr int NT2 = (B * N / kElems) < 64 ? 64 : (B * N / kElems);
     static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
     static constexpr size_t LDS1_BYTES = (size_t)LDS1 * sizeof(double2);   // float64 accumulation
     static constexpr int LDS2 = lds_padded_elems_c(B * N);                 // complex elements
     // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer
     static constexpr bool NM1_LDS =
-        (size_t)LDS2 * 2 * sizeof(R) + sizeof(double) * 16 * NT2 <= 160 * 1024;
+        (size_t)LDS2 * 2 * sizeof(R) + sizeof(double) * kElems * NT2 <= 160 * 1024;
     static constexpr size_t LDS2_BYTES =
-        (size_t)LDS2 * 2 * sizeof(R) + (NM1_LDS ? sizeof(double) * 16 * NT2 : 0);
+        (size_t)LDS2 * 2 * sizeof(R) + (NM1_LDS ? sizeof(double) * kElems * NT2 : 0);
 };
 
 // ---------------------------------------------------------------------------------------
@@ -400,8 +453,7 @@ template <typename R, bool FFT, int LOG2N>
 __device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned char* smem_raw,
                                            const uint32_t* __restrict__ offsets,
                                            const uint32_t* __restrict__ rec_cell,
-                                           const typename Cx<R>::T* __restrict__ rec_frac,
-                                           const typename Cx<R>::T* __restrict__ rec_vis,
+                                           const void* __restrict__ rec,
                                            const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
                                            typename Cx<R>::T* __restrict__ out) {
     using C = typename Cx<R>::T;
@@ -424,15 +476,14 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned
         const uint32_t beg = offsets[(size_t)(k * g.S + sp) << kLogReplicas];
         const uint32_t end = offsets[(size_t)(k * g.S + sp + 1) << kLogReplicas];
         for (uint32_t r = beg + tid; r < end; r += NT) {
-            const uint32_t cell = rec_cell[r];
-            const int q0 = (int)(cell & 0xFFFFu), p0 = (int)(cell >> 16);
+            int q0, p0;
+            C fr, v;
+            load_record<R>(rec_cell, rec, r, sp, LOG2H, q0, p0, fr, v);
             int b_lo = row0 - p0;
             if (b_lo < 0) b_lo = 0;
             int b_hi = row0 + H - 1 - p0;
             if (b_hi > W - 1) b_hi = W - 1;
             if (b_lo > b_hi) continue;
-            const C fr = rec_frac[r];
-            const C v = rec_vis[r];
             R gx[kMaxSupport];
 #pragma unroll
             for (int a = 0; a < kMaxSupport; ++a)
@@ -456,23 +507,29 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned
 
     if constexpr (FFT) {
         if constexpr (sizeof(R) == 4) {
-            // float64 strip -> float32 strip in the same LDS (all reads before any write)
-            constexpr int PER = (elems + NT - 1) / NT;
-            double2 t[PER];
+            // float64 strip -> float32 strip in the same LDS, in two halves: the floats of the
+            // first half land on doubles this half reads (so a barrier between read and write),
+            // those of the second half on doubles the first half already consumed.
+            constexpr int HALF = elems / 2;
+            constexpr int PER = (HALF + NT - 1) / NT;
 #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int e = tid + i * NT;
-                if (e < elems) t[i] = acc[lds_pad(e)];
-            }
-            __syncthreads();
+            for (int h = 0; h < 2; ++h) {
+                double2 t[PER];
 #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int e = tid + i * NT;
-                if (e < elems) lds[lds_pad(e)] = cmake<C>((R)t[i].x, (R)t[i].y);
+                for (int i = 0; i < PER; ++i) {
+                    const int e = h * HALF + tid + i * NT;
+                    if (tid + i * NT < HALF) t[i] = acc[lds_pad(e)];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < PER; ++i) {
+                    const int e = h * HALF + tid + i * NT;
+                    if (tid + i * NT < HALF) lds[lds_pad(e)] = cmake<C>((R)t[i].x, (R)t[i].y);
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
-        fft_rows_lds<LOG2N, H, NT>(lds, tw);
+        fft_rows_lds<LOG2N, kLogRadix, H, NT>(lds, tw);
         // column-block layout [k][jb][p'][B], p' = (p + n/2) mod n: the next pass reads a
         // contiguous [n][B] block per plane.  Image column j takes FFT bin (j + n/2) mod n.
         constexpr int B = SH::B, LOG2B = Log2Of<B>::value_any;
@@ -499,8 +556,7 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned
 template <typename R, int LOG2N>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
 k_grid_only(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restrict__ occ,
-            const uint32_t* __restrict__ rec_cell, const typename Cx<R>::T* __restrict__ rec_frac,
-            const typename Cx<R>::T* __restrict__ rec_vis, const R* __restrict__ kbc,
+            const uint32_t* __restrict__ rec_cell, const void* __restrict__ rec, const R* __restrict__ kbc,
             typename Cx<R>::T* __restrict__ out) {
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
@@ -512,7 +568,7 @@ k_grid_only(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
         for (int e = threadIdx.x; e < SH::H * SH::N; e += SH::NT1) dst[e] = cmake<C>((R)0, (R)0);
         return;
     }
-    grid_strip<R, false, LOG2N>(g, k, s, smem_raw, offsets, rec_cell, rec_frac, rec_vis, kbc, nullptr, out);
+    grid_strip<R, false, LOG2N>(g, k, s, smem_raw, offsets, rec_cell, rec, kbc, nullptr, out);
 }
 
 // Gridding + row FFT: a persistent grid walks the work list of occupied strips (heavy ones
@@ -521,8 +577,7 @@ template <typename R, int LOG2N>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
 k_grid_rows(Geom g, int nb, Scalars* __restrict__ sc, const uint32_t* __restrict__ list,
             const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
-            const typename Cx<R>::T* __restrict__ rec_frac, const typename Cx<R>::T* __restrict__ rec_vis,
-            const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
+            const void* __restrict__ rec, const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
             typename Cx<R>::T* __restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item;
@@ -540,7 +595,7 @@ k_grid_rows(Geom g, int nb, Scalars* __restrict__ sc, const uint32_t* __restrict
         __syncthreads();
         if (b < 0) break;
         const int k = b / g.S, s = b - k * g.S;
-        grid_strip<R, true, LOG2N>(g, k, s, smem_raw, offsets, rec_cell, rec_frac, rec_vis, kbc, tw, out);
+        grid_strip<R, true, LOG2N>(g, k, s, smem_raw, offsets, rec_cell, rec, kbc, opaque_ptr(tw), out);
         __syncthreads();
     }
 }
@@ -548,9 +603,9 @@ k_grid_rows(Geom g, int nb, Scalars* __restrict__ sc, const uint32_t* __restrict
 // ---------------------------------------------------------------------------------------
 // column FFTs, w-phase, stacking over planes, taper
 //
-// Work-group = one block of B image columns, 16 pixels per thread.  Per plane:
-//   * the inputs of the first radix-16 pass come straight from HBM into registers (thread
-//     tid = b * B + c takes column c at rows b + m N/16, so a wave reads 64 consecutive
+// Work-group = one block of B image columns, 8 pixels per thread.  Per plane:
+//   * the inputs of the first radix-8 pass come straight from HBM into registers (thread
+//     tid = b * B + c takes column c at rows b + m N/8, so a wave reads 64 consecutive
 //     elements of the contiguous [n][B] block); rows of empty strips read as 0;
 //   * the middle passes run in LDS, the last pass leaves its outputs in registers;
 //   * each output is multiplied by exp(+2 pi i w_k (n - 1)) and its real part summed over
@@ -565,14 +620,14 @@ __device__ __forceinline__ void pass2_load(const typename Cx<R>::T* __restrict__
                                            const uint8_t* __restrict__ occk, int tid, bool active,
                                            int log2H, typename Cx<R>::T* x) {
     using C = typename Cx<R>::T;
-    constexpr int n = 1 << LOG2N, hn = n >> 1, n16 = n >> 4;
+    constexpr int n = 1 << LOG2N, hn = n >> 1, nr = n >> kLogRadix;
     const int b = tid / B;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < kElems; ++m) {
         x[m] = cmake<C>((R)0, (R)0);
-        const int pp = b + m * n16;
+        const int pp = b + m * nr;
         const int p = (pp + hn) & (n - 1);
-        if (active && occk[p >> log2H]) x[m] = src[m * n16 * B + tid];
+        if (active && occk[p >> log2H]) x[m] = src[m * nr * B + tid];
     }
 }
 
@@ -587,27 +642,29 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     constexpr int n = SH::N, nmask = n - 1, hn = n >> 1;
     constexpr int B = SH::B, NT = SH::NT2, LOG2B = Log2Of<B>::value_any;
     constexpr int elems = B * n;
+    constexpr int E = kElems;
+    static_assert(LOG2N > kLogRadix, "image side must exceed the base radix");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* lds = reinterpret_cast<C*>(smem_raw);
     // n - 1 of each output slot: in LDS after the FFT buffer (nm1s[s * NT + tid]) when it
     // fits there, else in registers
     double* nm1s = reinterpret_cast<double*>(lds + SH::LDS2);
-    double nm1r[SH::NM1_LDS ? 1 : 16];
+    double nm1r[SH::NM1_LDS ? 1 : E];
     nm1r[0] = 0.0;
     const int jb = blockIdx.x;
     const int tid = threadIdx.x;
-    const bool first_active = tid < (elems >> 4);
+    const bool first_active = tid < (elems >> kLogRadix);
 
     // comp is the Kahan compensation (float only)
-    R acc[16], comp[sizeof(R) == 4 ? 16 : 1];
+    R acc[E], comp[sizeof(R) == 4 ? E : 1];
     comp[0] = (R)0;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < E; ++s) {
         acc[s] = (R)0;
         if constexpr (sizeof(R) == 4) comp[s] = (R)0;
         int c, ip;
         double v = 0.0;
-        if (last_slot<LOG2N, B, NT>(tid, s, c, ip)) {
+        if (last_slot<LOG2N, kLogRadix, B, NT>(tid, s, c, ip)) {
             const int i = (ip + hn) & nmask, j = (jb << LOG2B) + c;
             const double l = (double)(j - hn) * g.pixel, m = (double)(i - hn) * g.pixel;
             const double r2 = m * m + l * l;
@@ -620,7 +677,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
 
     int k = 0;
     while (k < g.nw && !plane_occ[k]) ++k;
-    C x[16], pf[16];
+    C x[E], pf[E];
     if (k < g.nw)
         pass2_load<R, LOG2N, B>(inter + ((size_t)k << (2 * LOG2N)) + (size_t)jb * elems,
                                 occ + (size_t)k * g.S, tid, first_active, g.log2H, pf);
@@ -628,34 +685,31 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         int kn = k + 1;
         while (kn < g.nw && !plane_occ[kn]) ++kn;
 #pragma unroll
-        for (int m = 0; m < 16; ++m) x[m] = pf[m];
+        for (int m = 0; m < E; ++m) x[m] = pf[m];
         if constexpr (Pass2Prefetch<R>::value) {
             if (kn < g.nw)
                 pass2_load<R, LOG2N, B>(inter + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
                                         occ + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
         }
-        if constexpr (LOG2N > 4) {
-            // first pass: radix 16 with L = 1 (no twiddles), registers to LDS
-            if (first_active) {
-                dft16(x);
-                const int c = tid % B, b = tid / B;
-                const int base = (c << LOG2N) + (b << 4);
+        // first pass: radix 8 with L = 1 (no twiddles), registers to LDS
+        if (first_active) {
+            dft8(x);
+            const int c = tid % B, b = tid / B;
+            const int base = (c << LOG2N) + (b << kLogRadix);
 #pragma unroll
-                for (int m = 0; m < 16; ++m) lds[lds_pad(base + m)] = x[m];
-            }
-            __syncthreads();
-            stockham_range<LOG2N, 4, FftPlan<LOG2N>::LAST_L, B, NT>(lds, tw);
-            fft_last_to_regs<LOG2N, B, NT>(lds, tw, x);
-        } else {
-            if (first_active) dft16(x);   // n = 16: one pass, x[m] is bin m of column tid
+            for (int m = 0; m < E; ++m) lds[lds_pad(base + m)] = x[m];
         }
+        __syncthreads();
+        const C* twk = opaque_ptr(tw);
+        stockham_range<LOG2N, kLogRadix, kLogRadix, FftPlan<LOG2N, kLogRadix>::LAST_L, B, NT>(lds, twk);
+        fft_last_to_regs<LOG2N, kLogRadix, B, NT>(lds, twk, x);
         double wk;
         {
 #pragma clang fp contract(off)
             wk = w_lo + ((double)k + 0.5) * dw;
         }
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
+        for (int s = 0; s < E; ++s) {
             double cyc = wk * (SH::NM1_LDS ? nm1s[s * NT + tid] : nm1r[SH::NM1_LDS ? 0 : s]);
             cyc -= rint(cyc);
             R sn, cs;
@@ -688,9 +742,9 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
 
     const R inv_sw = sum_w > 0.0 ? (R)(1.0 / sum_w) : (R)0;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < E; ++s) {
         int c, ip;
-        if (last_slot<LOG2N, B, NT>(tid, s, c, ip)) {
+        if (last_slot<LOG2N, kLogRadix, B, NT>(tid, s, c, ip)) {
             const int i = (ip + hn) & nmask, j = (jb << LOG2B) + c;
             image[(size_t)i * n + j] = sum_w > 0.0 ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
         }

@@ -61,7 +61,7 @@ struct wsimg_plan {
     uint32_t* list = nullptr;      // work list of occupied strips
     int persist_blocks = 256;      // work-groups of the persistent gridding kernel
     uint32_t *key = nullptr, *rank = nullptr, *rec_cell = nullptr;
-    void *rec_frac = nullptr, *rec_vis = nullptr, *inter = nullptr;
+    void *rec = nullptr, *inter = nullptr;
     void *tw = nullptr, *inv_taper = nullptr, *kbc = nullptr;
     int64_t device_bytes = 0;
     std::vector<void*> allocations;
@@ -183,12 +183,12 @@ wsimg_status launch_grid_rows(wsimg_plan* pl, bool fft, void* out) {
     if (fft) {
         hipLaunchKernelGGL((k_grid_rows<R, LOG2N>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1), pl->lds1,
                            pl->stream, g, (int)pl->nb, pl->scalars, pl->list, pl->offsets, pl->rec_cell,
-                           (const C*)pl->rec_frac, (const C*)pl->rec_vis, (const R*)pl->kbc, (const C*)pl->tw,
+                           (const void*)pl->rec, (const R*)pl->kbc, (const C*)pl->tw,
                            (C*)out);
     } else {
         hipLaunchKernelGGL((k_grid_only<R, LOG2N>), dim3((unsigned)(g.nw * g.S)), dim3(pl->nt1), pl->lds1,
-                           pl->stream, g, pl->offsets, pl->occ, pl->rec_cell, (const C*)pl->rec_frac,
-                           (const C*)pl->rec_vis, (const R*)pl->kbc, (C*)out);
+                           pl->stream, g, pl->offsets, pl->occ, pl->rec_cell, (const void*)pl->rec,
+                           (const R*)pl->kbc, (C*)out);
     }
     WS_LAUNCH_CHECK("grid_rows");
     return WSIMG_OK;
@@ -313,7 +313,7 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, c
     if (M > 0) {
         hipLaunchKernelGGL((k_scatter<R, R>), dim3(blocks_for(M, 256)), dim3(256), 0, s, M, uvw,
                            (const C*)vis, (const R*)wts, freq, g, pl->key, pl->rank, pl->offsets,
-                           pl->rec_cell, (C*)pl->rec_frac, (C*)pl->rec_vis);
+                           pl->rec_cell, pl->rec);
         WS_LAUNCH_CHECK("scatter");
     }
     if (auto r = st.after(4)) return r;
@@ -445,9 +445,8 @@ wsimg_status wsimg_plan_create(wsimg_plan** out, const wsimg_params* p, int64_t 
     ALLOC(plane_occ, (size_t)g.nw, "plane occupancy");
     ALLOC(key, sizeof(uint32_t) * mv, "keys");
     ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
-    ALLOC(rec_cell, sizeof(uint32_t) * mv, "record cells");
-    ALLOC(rec_frac, pl->cbytes * mv, "record offsets");
-    ALLOC(rec_vis, pl->cbytes * mv, "record visibilities");
+    ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * mv, "record cells");
+    ALLOC(rec, (f32 ? 16 : 32) * mv, "records");
     ALLOC(inter, pl->cbytes * cells, "row-transformed planes");
     ALLOC(tw, pl->cbytes * n, "twiddles");
     ALLOC(inv_taper, pl->rbytes * n, "taper");

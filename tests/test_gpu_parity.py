@@ -321,3 +321,43 @@ def test_c3_geometry_full_grid(oracle_mod):
     e32 = np.max(np.abs(img32[np.ix_(rows, cols)] - ref)) / scale
     print(f"c3 sampled vs oracle: f64 {e64:.3e} f32 {e32:.3e}")
     assert e64 <= 1e-12 and e32 <= 1e-5
+
+
+# ---------------------------------------------------------------------------------------
+# properties of the GPU path itself (any size)
+
+def test_gpu_linearity_permutation_and_weight_scale(c1):
+    """The image is linear in V, independent of row order, and unchanged by scaling all
+    weights (natural weighting divides by their sum)."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision("f64")
+    uvw, vis, w = _dev(ds, torch)
+    kw = dict(n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta)
+    rng = np.random.default_rng(21)
+    v2 = torch.from_numpy(rng.normal(size=ds.m) + 1j * rng.normal(size=ds.m)).to(vis.device)
+    a, b = 0.7, -1.9
+    D1 = ws.image(uvw, vis, w, ds.freq_hz, **kw).cpu().numpy()
+    D2 = ws.image(uvw, v2, w, ds.freq_hz, **kw).cpu().numpy()
+    D12 = ws.image(uvw, (a * vis + b * v2).contiguous(), w, ds.freq_hz, **kw).cpu().numpy()
+    assert np.max(np.abs(D12 - (a * D1 + b * D2))) <= 1e-12 * np.max(np.abs(D12))
+    perm = torch.from_numpy(rng.permutation(ds.m)).to(vis.device)
+    Dp = ws.image(uvw[perm].contiguous(), vis[perm].contiguous(), w[perm].contiguous(), ds.freq_hz,
+                  **kw).cpu().numpy()
+    assert np.max(np.abs(Dp - D1)) <= 1e-12 * np.max(np.abs(D1))
+    Ds = ws.image(uvw, vis, (3.25 * w).contiguous(), ds.freq_hz, **kw).cpu().numpy()
+    assert np.max(np.abs(Ds - D1)) <= 1e-12 * np.max(np.abs(D1))
+
+
+def test_plan_reuse_with_fewer_rows(oracle_mod, c1):
+    """One plan, sized for all rows, imaging a prefix and then the whole set."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision("f32")
+    uvw, vis, w = _dev(ds, torch)
+    with ws.Plan(ds.n, ds.pixel_rad, ds.n_wplanes, ds.support, ds.beta, "f32", max_vis=ds.m) as p:
+        for m in (ds.m // 3, ds.m):
+            img = p.image(uvw[:m].contiguous(), vis[:m].contiguous(), w[:m].contiguous(), ds.freq_hz).cpu().numpy()
+            sub = ds.subset(slice(0, m))
+            ref = oracle_mod.wstack_image(sub.uvw_m, sub.vis, sub.weights, sub.freq_hz, _prm(oracle_mod, sub))
+            _check(oracle_mod, img, ref, ds.n, ds.support, ds.beta, 1e-5, full=True, tag=f"prefix {m}")
