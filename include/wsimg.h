@@ -87,6 +87,7 @@ typedef struct {
     int64_t n_buckets;       /* sort buckets: n_wplanes * n / strip_rows                   */
     int64_t max_vis;
     int64_t device_bytes;    /* device memory the plan holds                               */
+    int64_t max_channels;    /* channels one wsimg_image_batch call may image              */
 } wsimg_plan_info;
 
 #define WSIMG_N_KERNELS 7
@@ -109,6 +110,22 @@ typedef struct wsimg_plan wsimg_plan;
  */
 wsimg_status wsimg_plan_create(wsimg_plan **out, const wsimg_params *p, int64_t max_vis,
                                void *hip_stream);
+
+/*
+ * A plan that images up to max_channels channels (frequencies) of one geometry in one call
+ * (wsimg_image_batch).  Every channel has its own w-plane range, planes and image; the
+ * channels share the launches: each stage covers all channels of the call, and the gridding
+ * work list spans the occupied strips of every channel, so many small channels fill the GPU
+ * the way one large one does.
+ *  max_vis      : largest total row count of a call (all channels), 0 .. 4294967294.
+ *  max_channels : 1 .. 65535.  The plan's device scratch grows with it: the row-transformed
+ *                 planes take max_channels * n_wplanes * n * n complex elements, the sort
+ *                 counters 256 bytes per (channel, plane, strip).
+ * Errors: as wsimg_plan_create; WSIMG_E_UNSUPPORTED when max_channels * n_wplanes * strips
+ *         exceeds 2^25 sort buckets.
+ */
+wsimg_status wsimg_plan_create_batch(wsimg_plan **out, const wsimg_params *p, int64_t max_vis,
+                                     int32_t max_channels, void *hip_stream);
 
 /* Release a plan and its device memory (waits for its stream).  NULL is a no-op. */
 wsimg_status wsimg_plan_destroy(wsimg_plan *plan);
@@ -142,6 +159,28 @@ wsimg_status wsimg_plan_get_info(const wsimg_plan *plan, wsimg_plan_info *info);
 wsimg_status wsimg_image(wsimg_plan *plan, int64_t n_vis, const double *uvw_m,
                          const void *vis, const void *weights, double freq_hz,
                          void *image_out, wsimg_stats *stats);
+
+/*
+ * Dirty images of n_channels channels, each exactly as wsimg_image would make it from that
+ * channel's rows and frequency (the many frequency planes of the abstract and conclusions,
+ * imaged one channel at a time by Eqs. 1-3).
+ *  n_channels : 1 .. the plan's max_channels.
+ *  row_counts : host, [n_channels]; channel c owns rows [sum of the counts before c,
+ *               that sum + row_counts[c]) of the inputs; the total is at most max_vis.
+ *  uvw_m, vis, weights : device, the rows of all channels, channel after channel, laid out
+ *               as in wsimg_image.
+ *  freqs_hz   : host, [n_channels], each > 0 and finite.
+ *  images_out : device, [n_channels][n][n] of the plan's real type; fully overwritten.
+ *  stats      : NULL, or host [n_channels] receiving each channel's counters (the call then
+ *               waits for the stream).
+ * The host arrays are read before the call returns.  A channel whose kept weights sum to zero
+ * gets an all-zero image; with stats the call then returns WSIMG_E_EMPTY after writing every
+ * channel's image and counters.
+ * Errors: WSIMG_E_INVALID, WSIMG_E_CAPACITY, WSIMG_E_HIP, WSIMG_E_EMPTY.
+ */
+wsimg_status wsimg_image_batch(wsimg_plan *plan, int32_t n_channels, const int64_t *row_counts,
+                               const double *uvw_m, const void *vis, const void *weights,
+                               const double *freqs_hz, void *images_out, wsimg_stats *stats);
 
 /*
  * The gridding step alone (Eq. 3 with the separable kernel, nearest w-plane):

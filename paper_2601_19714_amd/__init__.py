@@ -52,7 +52,7 @@ class Plan:
 
     def __init__(self, n: int, pixel_rad: float, n_wplanes: int, support: int = 7,
                  beta: Optional[float] = None, precision: str = "f32", max_vis: int = 0,
-                 w_range: Optional[Tuple[float, float]] = None, device=None):
+                 w_range: Optional[Tuple[float, float]] = None, device=None, max_channels: int = 1):
         import torch
 
         self._torch = torch
@@ -73,9 +73,10 @@ class Plan:
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            _check(self._L.wsimg_plan_create(ctypes.byref(self._h), ctypes.byref(p), int(max_vis),
-                                             ctypes.c_void_p(stream)))
+            _check(self._L.wsimg_plan_create_batch(ctypes.byref(self._h), ctypes.byref(p), int(max_vis),
+                                                   int(max_channels), ctypes.c_void_p(stream)))
         self.max_vis = int(max_vis)
+        self.max_channels = int(max_channels)
 
     # -- helpers -------------------------------------------------------------------------
     def _dtypes(self):
@@ -124,6 +125,36 @@ class Plan:
         elif out.dtype != rdt or out.shape != (self.n, self.n) or not out.is_contiguous() or out.device != self.device:
             raise ValueError("out must be a contiguous [n, n] tensor of the plan's real dtype on its device")
         return self._run(self._L.wsimg_image, uvw, vis, weights, freq_hz, out, stats)
+
+    def image_batch(self, uvw, vis, weights, row_counts, freqs_hz, out=None, stats: bool = False):
+        """Dirty images [n_channels, n, n] of the channels laid out one after another in the
+        inputs: channel c owns the next row_counts[c] rows and has frequency freqs_hz[c]
+        (wsimg_image_batch).  With stats=True returns (images, [stats dict per channel])."""
+        _, rdt = self._dtypes()
+        counts = [int(x) for x in row_counts]
+        freqs = [float(x) for x in freqs_hz]
+        nch = len(counts)
+        if nch != len(freqs) or nch < 1:
+            raise ValueError("row_counts and freqs_hz must have the same, non-zero length")
+        m = self._args(uvw, vis, weights)
+        if sum(counts) != m:
+            raise ValueError(f"row_counts sum to {sum(counts)}, the inputs hold {m} rows")
+        shape = (nch, self.n, self.n)
+        if out is None:
+            out = self._torch.empty(shape, dtype=rdt, device=self.device)
+        elif out.dtype != rdt or tuple(out.shape) != shape or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous [n_channels, n, n] tensor of the plan's real dtype")
+        self._stream()
+        c_counts = (ctypes.c_int64 * nch)(*counts)
+        c_freqs = (ctypes.c_double * nch)(*freqs)
+        st = (_lib.Stats * nch)()
+        status = self._L.wsimg_image_batch(self._h, nch, c_counts, ctypes.c_void_p(uvw.data_ptr()),
+                                           ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(weights.data_ptr()),
+                                           c_freqs, ctypes.c_void_p(out.data_ptr()), st if stats else None)
+        _check(status)
+        if stats:
+            return out, [{f: getattr(st[c], f) for f, _ in _lib.Stats._fields_} for c in range(nch)]
+        return out
 
     def grid(self, uvw, vis, weights, freq_hz: float, out=None, stats: bool = False):
         """The gridding step alone: complex grid [n_wplanes, n, n] (wsimg_grid)."""

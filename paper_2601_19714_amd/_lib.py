@@ -22,8 +22,8 @@ WSIMG_N_KERNELS = 7
 
 # every symbol include/wsimg.h declares
 EXPORTS = (
-    "wsimg_plan_create", "wsimg_plan_destroy", "wsimg_plan_set_stream", "wsimg_plan_get_info",
-    "wsimg_image", "wsimg_grid", "wsimg_set_timing", "wsimg_read_timing", "wsimg_stage_name",
+    "wsimg_plan_create", "wsimg_plan_create_batch", "wsimg_plan_destroy", "wsimg_plan_set_stream",
+    "wsimg_plan_get_info", "wsimg_image", "wsimg_image_batch", "wsimg_grid", "wsimg_set_timing", "wsimg_read_timing", "wsimg_stage_name",
     "wsimg_status_string", "wsimg_last_error", "wsimg_version",
 )
 
@@ -44,7 +44,8 @@ class Stats(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("strip_rows", ctypes.c_int32), ("col_block", ctypes.c_int32),
-                ("n_buckets", ctypes.c_int64), ("max_vis", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("n_buckets", ctypes.c_int64), ("max_vis", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("max_channels", ctypes.c_int64)]
 
 
 class Timing(ctypes.Structure):
@@ -65,15 +66,19 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.wsimg_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), i64, vp]
+    L.wsimg_plan_create_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), i64, i32, vp]
     L.wsimg_plan_destroy.argtypes = [vp]
     L.wsimg_plan_set_stream.argtypes = [vp, vp]
     L.wsimg_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     for f in (L.wsimg_image, L.wsimg_grid):
         f.argtypes = [vp, i64, vp, vp, vp, dbl, vp, ctypes.POINTER(Stats)]
+    L.wsimg_image_batch.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, ctypes.POINTER(dbl), vp,
+                                    ctypes.POINTER(Stats)]
     L.wsimg_set_timing.argtypes = [vp, i32]
     L.wsimg_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
-    for f in (L.wsimg_plan_create, L.wsimg_plan_destroy, L.wsimg_plan_set_stream, L.wsimg_plan_get_info,
-              L.wsimg_image, L.wsimg_grid, L.wsimg_set_timing, L.wsimg_read_timing):
+    for f in (L.wsimg_plan_create, L.wsimg_plan_create_batch, L.wsimg_plan_destroy, L.wsimg_plan_set_stream,
+              L.wsimg_plan_get_info, L.wsimg_image, L.wsimg_image_batch, L.wsimg_grid, L.wsimg_set_timing,
+              L.wsimg_read_timing):
         f.restype = ctypes.c_int
     L.wsimg_stage_name.argtypes = [i32]
     L.wsimg_stage_name.restype = ctypes.c_char_p

@@ -17,6 +17,12 @@
 //  k_cols_stack   : one work-group per block of image columns: for each plane, column FFTs
 //                   in LDS, multiply by the plane's w-phase, Kahan-accumulate the real part;
 //                   finally divide by the taper on both axes and the sum of weights.
+//
+// Every stage carries a channel index: a call images one or more channels (frequencies) at
+// once.  The rows of channel c are rows [row_off[c], row_off[c+1]) of the inputs; each
+// channel has its own plane range, sum of weights, buckets, intermediate and image.  Row
+// kernels run on a grid whose y index is the channel; the gridding work list spans all
+// channels.
 #pragma once
 
 #include "device_common.hpp"
@@ -28,18 +34,29 @@ namespace wsimg {
 struct Geom {
     int n, log2n, nw, support, half;
     int H, log2H, S;        // grid rows per strip, strips per plane
+    int nb1;                // buckets per channel: nw * S
     int B, log2B, NB;       // image columns per stacking block, blocks
     int fixed_range;
     double du, half_n, pixel;
     double w_lo_fixed, w_hi_fixed;
 };
 
-// Written by k_finalize, read by the later stages.
+// Per-call channel table (device arrays).
+struct Chan {
+    const int64_t* row_off;   // [nch + 1]: rows of channel c are [row_off[c], row_off[c + 1])
+    const double* freq;       // [nch], Hz
+};
+
+// Per channel, written by k_finalize (and k_occupancy's counts), read by the later stages.
 struct Scalars {
     double w_lo, w_hi, dw, sum_w;
     unsigned long long n_kept, n_in, n_occ, n_planes;
-    // work list of occupied strips: heavy ones from the front, light ones from the back
-    unsigned int n_heavy, n_light, work_next, pad;
+};
+
+// The gridding work list of occupied strips of all channels: heavy ones from the front,
+// light ones from the back; next is the persistent kernel's fetch counter.
+struct WorkList {
+    unsigned int n_heavy, n_light, next, pad;
 };
 
 struct Partial {
@@ -83,13 +100,16 @@ __device__ __forceinline__ double wave_reduce_max(double v) {
     return v;
 }
 
-// Block of 256 threads; block b covers rows [b*chunk, min(M, (b+1)*chunk)).
+// Block (b, c) of 256 threads covers rows [b*chunk, min(count_c, (b+1)*chunk)) of channel c.
 template <typename WT>
 __global__ void __launch_bounds__(256)
-k_reduce(int64_t M, int64_t chunk, const double* __restrict__ uvw, const WT* __restrict__ wts,
-         double freq, Geom g, Partial* __restrict__ part) {
-    const int64_t beg = blockIdx.x * chunk;
-    const int64_t end = beg + chunk < M ? beg + chunk : M;
+k_reduce(Chan ch, int64_t chunk, int nparts, const double* __restrict__ uvw, const WT* __restrict__ wts,
+         Geom g, Partial* __restrict__ part) {
+    const int c = blockIdx.y;
+    const int64_t r1 = ch.row_off[c + 1];
+    const int64_t beg = ch.row_off[c] + blockIdx.x * chunk;
+    const int64_t end = beg + chunk < r1 ? beg + chunk : r1;
+    const double freq = ch.freq[c];
     double wmin = INFINITY, wmax = -INFINITY, sw = 0.0;
     unsigned long long nk = 0;
     for (int64_t m = beg + threadIdx.x; m < end; m += blockDim.x) {
@@ -117,20 +137,24 @@ k_reduce(int64_t M, int64_t chunk, const double* __restrict__ uvw, const WT* __r
             t.sumw += sh[i].sumw;
             t.nk += sh[i].nk;
         }
-        part[blockIdx.x] = t;
+        part[(size_t)c * nparts + blockIdx.x] = t;
     }
 }
 
-// One block of 256 threads; fixed summation order, so the sum of weights is reproducible.
+// One block of 256 threads per channel; fixed summation order, so the sum of weights is
+// reproducible.  Block 0 also resets the work list.
 __global__ void __launch_bounds__(256)
-k_finalize(int nparts, const Partial* __restrict__ part, Geom g, int64_t M, Scalars* __restrict__ sc) {
+k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalars* __restrict__ sc,
+           WorkList* __restrict__ wl) {
     __shared__ double s_sw[256], s_min[256], s_max[256];
     __shared__ unsigned long long s_nk[256];
+    const int c = blockIdx.x;
+    const Partial* pc = part + (size_t)c * nparts;
     double sw = 0.0, mn = INFINITY, mx = -INFINITY;
     unsigned long long nk = 0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        sw += part[i].sumw; nk += part[i].nk;
-        mn = fmin(mn, part[i].wmin); mx = fmax(mx, part[i].wmax);
+        sw += pc[i].sumw; nk += pc[i].nk;
+        mn = fmin(mn, pc[i].wmin); mx = fmax(mx, pc[i].wmax);
     }
     s_sw[threadIdx.x] = sw; s_min[threadIdx.x] = mn; s_max[threadIdx.x] = mx; s_nk[threadIdx.x] = nk;
     __syncthreads();
@@ -152,51 +176,50 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, int64_t M, Scal
         r.dw = (r.w_hi - r.w_lo) / (double)g.nw;
         r.sum_w = s_sw[0];
         r.n_kept = s_nk[0];
-        r.n_in = (unsigned long long)M;
+        r.n_in = (unsigned long long)(ch.row_off[c + 1] - ch.row_off[c]);
         r.n_occ = 0;
         r.n_planes = 0;
-        r.n_heavy = 0;
-        r.n_light = 0;
-        r.work_next = 0;
-        r.pad = 0;
-        *sc = r;
+        sc[c] = r;
+        if (c == 0) *wl = WorkList{0u, 0u, 0u, 0u};
     }
 }
 
-// Bucket counters are replicated kReplicas times, laid out [bucket][replica]; row m counts
-// in replica (m / 256) mod kReplicas.  (Blocks of consecutive rows, not single rows: a
-// bucket's records keep their time-major order, so the lanes of a gridding wave hold
-// different baselines and rarely hit the same cell.)  The rows of one hot bucket (tens of thousands near the
-// uv-plane centre) then spread their atomics over kReplicas addresses instead of one, and
-// the bucket's rows still end up contiguous after the scan.
+// Bucket counters are replicated kReplicas times, laid out [bucket][replica]; the rows of
+// row block b of a channel (256 rows) count in replica b mod kReplicas.  The rows of one hot
+// bucket (tens of thousands near the uv-plane centre) then spread their atomics over
+// kReplicas addresses instead of one, and the bucket's rows still end up contiguous after
+// the scan.  (Blocks of consecutive rows, not single rows: a bucket's records keep their
+// time-major order, so the lanes of a gridding wave hold different baselines and rarely hit
+// the same cell.)  Bucket id: channel * nb1 + plane * S + strip.
 constexpr int kReplicas = 64;
 constexpr int kLogReplicas = 6;
-__device__ __forceinline__ uint32_t row_replica(int64_t m) { return (uint32_t)(m >> 8) & (kReplicas - 1); }
 
 // Ranks are taken once per distinct key in a wave: the lanes sharing a key elect a leader,
 // which adds their count to the counter; each lane's rank is the returned base plus the
 // number of lower lanes with the same key.
 template <typename WT>
 __global__ void __launch_bounds__(256)
-k_key(int64_t M, const double* __restrict__ uvw, const WT* __restrict__ wts, double freq, Geom g,
+k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom g,
       const Scalars* __restrict__ sc, uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
       uint32_t* __restrict__ counts) {
-    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool in = m < M;
+    const int c = blockIdx.y;
+    const int64_t r0 = ch.row_off[c], r1 = ch.row_off[c + 1];
+    if ((int64_t)blockIdx.x * blockDim.x >= r1 - r0) return;       // whole block past the channel
+    const int64_t m = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = m < r1;
     uint32_t kk = 0xFFFFFFFFu;
     if (in) {
         const double wt = (double)wts[m];
-        RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
+        RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support);
         if (rg.keep) {
-            const int k = plane_index(rg.w, sc->w_lo, sc->dw, g.nw);
+            const int k = plane_index(rg.w, sc[c].w_lo, sc[c].dw, g.nw);
             const int p0 = (int)rg.cy - g.half;
-            kk = (uint32_t)(k * g.S + (p0 >> g.log2H));
+            kk = (uint32_t)(c * g.nb1 + k * g.S + (p0 >> g.log2H));
         }
     }
     const int lane = threadIdx.x & 63;
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // all lanes of a block share the replica (m / 256 is uniform in a 256-thread block)
-    const uint32_t rep = row_replica((int64_t)blockIdx.x * blockDim.x);
+    const uint32_t rep = blockIdx.x & (kReplicas - 1);
     unsigned long long todo = __ballot(kk != 0xFFFFFFFFu);
     uint32_t rr = 0;
     while (todo) {
@@ -297,21 +320,26 @@ k_scan_down(int64_t total, const uint32_t* __restrict__ counts, const uint32_t* 
 constexpr uint32_t kHeavyStrip = 4096;
 
 __global__ void __launch_bounds__(256)
-k_occupancy(int nb, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __restrict__ occ,
-            uint8_t* __restrict__ plane_occ, uint32_t* __restrict__ list, Scalars* __restrict__ sc) {
+k_occupancy(int nch, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __restrict__ occ,
+            uint8_t* __restrict__ plane_occ, uint32_t* __restrict__ list, Scalars* __restrict__ sc,
+            WorkList* __restrict__ wl) {
+    const int total = nch * g.nb1;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t o = 0, po = 0, visits = 0;
-    if (b < nb) {
-        const int k = b / g.S, sidx = b - k * g.S;
+    int c = 0;
+    if (b < total) {
+        c = b / g.nb1;
+        const int bb = b - c * g.nb1;
+        const int k = bb / g.S, sidx = bb - k * g.S;
+        const int base = c * g.nb1 + k * g.S;
         int slo = ((sidx << g.log2H) - (g.support - 1)) >> g.log2H;
         if (slo < 0) slo = 0;
-        visits = offsets[(size_t)(k * g.S + sidx + 1) << kLogReplicas] -
-                 offsets[(size_t)(k * g.S + slo) << kLogReplicas];
+        visits = offsets[(size_t)(base + sidx + 1) << kLogReplicas] - offsets[(size_t)(base + slo) << kLogReplicas];
         o = visits > 0 ? 1u : 0u;
         occ[b] = (uint8_t)o;
         if (sidx == 0) {
-            po = offsets[(size_t)((k + 1) * g.S) << kLogReplicas] > offsets[(size_t)(k * g.S) << kLogReplicas] ? 1u : 0u;
-            plane_occ[k] = (uint8_t)po;
+            po = offsets[(size_t)(base + g.S) << kLogReplicas] > offsets[(size_t)base << kLogReplicas] ? 1u : 0u;
+            plane_occ[c * g.nw + k] = (uint8_t)po;
         }
     }
     const int lane = threadIdx.x & 63;
@@ -320,20 +348,27 @@ k_occupancy(int nb, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __res
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t hbase = 0, lbase = 0;
     if (lane == 0) {
-        if (heavy) hbase = atomicAdd(&sc->n_heavy, (unsigned)__popcll(heavy));
-        if (light) lbase = atomicAdd(&sc->n_light, (unsigned)__popcll(light));
+        if (heavy) hbase = atomicAdd(&wl->n_heavy, (unsigned)__popcll(heavy));
+        if (light) lbase = atomicAdd(&wl->n_light, (unsigned)__popcll(light));
     }
     hbase = __shfl(hbase, 0, 64);
     lbase = __shfl(lbase, 0, 64);
     if (o) {
         if (visits > kHeavyStrip) list[hbase + __popcll(heavy & below)] = (uint32_t)b;
-        else list[nb - 1 - (lbase + __popcll(light & below))] = (uint32_t)b;
+        else list[total - 1 - (lbase + __popcll(light & below))] = (uint32_t)b;
     }
-    o = wave_reduce_sum(o);
-    po = wave_reduce_sum(po);
-    if (lane == 0) {
-        if (o) atomicAdd(&sc->n_occ, (unsigned long long)o);
-        if (po) atomicAdd(&sc->n_planes, (unsigned long long)po);
+    // per-channel counts: one atomic per wave when the wave lies in one channel
+    const int c0 = __shfl(c, 0, 64);
+    if (__all(b >= total || c == c0)) {
+        o = wave_reduce_sum(o);
+        po = wave_reduce_sum(po);
+        if (lane == 0) {
+            if (o) atomicAdd(&sc[c0].n_occ, (unsigned long long)o);
+            if (po) atomicAdd(&sc[c0].n_planes, (unsigned long long)po);
+        }
+    } else {
+        if (o) atomicAdd(&sc[c].n_occ, 1ull);
+        if (po) atomicAdd(&sc[c].n_planes, 1ull);
     }
 }
 
@@ -353,18 +388,21 @@ __device__ __forceinline__ uint32_t frac_code(double f) {
 
 template <typename R, typename WT>
 __global__ void __launch_bounds__(256)
-k_scatter(int64_t M, const double* __restrict__ uvw, const typename Cx<R>::T* __restrict__ vis,
-          const WT* __restrict__ wts, double freq, Geom g, const uint32_t* __restrict__ key,
+k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __restrict__ vis,
+          const WT* __restrict__ wts, Geom g, const uint32_t* __restrict__ key,
           const uint32_t* __restrict__ rank, const uint32_t* __restrict__ offsets,
           uint32_t* __restrict__ rec_cell, void* __restrict__ rec) {
     using C = typename Cx<R>::T;
-    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (m >= M) return;
+    const int c = blockIdx.y;
+    const int64_t r0 = ch.row_off[c], r1 = ch.row_off[c + 1];
+    const int64_t m = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= r1) return;
     const uint32_t kk = key[m];
     if (kk == 0xFFFFFFFFu) return;
     const double wt = (double)wts[m];
-    RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
-    const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + row_replica(m)] + rank[m];
+    RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support);
+    const uint32_t rep = blockIdx.x & (kReplicas - 1);     // the row block's replica (as in k_key)
+    const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + rep] + rank[m];
     const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
     const C v = vis[m];
     const R w = (R)wts[m];
@@ -450,7 +488,7 @@ template <typename R, int LOG2N> struct Shape {
 // strip to float32 in place before its FFT.
 // One occupied strip (plane k, strip s) by the whole work-group.
 template <typename R, bool FFT, int LOG2N>
-__device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned char* smem_raw,
+__device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, unsigned char* smem_raw,
                                            const uint32_t* __restrict__ offsets,
                                            const uint32_t* __restrict__ rec_cell,
                                            const void* __restrict__ rec,
@@ -473,8 +511,9 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned
     if (s_lo < 0) s_lo = 0;
     constexpr int shift = FFT ? (n >> 1) : 0;   // place cell q at (q + n/2) mod n: the centring
     for (int sp = s_lo; sp <= s; ++sp) {
-        const uint32_t beg = offsets[(size_t)(k * g.S + sp) << kLogReplicas];
-        const uint32_t end = offsets[(size_t)(k * g.S + sp + 1) << kLogReplicas];
+        const int bucket = c * g.nb1 + k * g.S + sp;
+        const uint32_t beg = offsets[(size_t)bucket << kLogReplicas];
+        const uint32_t end = offsets[(size_t)(bucket + 1) << kLogReplicas];
         for (uint32_t r = beg + tid; r < end; r += NT) {
             int q0, p0;
             C fr, v;
@@ -534,17 +573,17 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned
         // contiguous [n][B] block per plane.  Image column j takes FFT bin (j + n/2) mod n.
         constexpr int B = SH::B, LOG2B = Log2Of<B>::value_any;
         const int pp0 = (row0 + (n >> 1)) & nmask;
-        C* dst = out + ((size_t)k << (2 * LOG2N));
+        C* dst = out + ((size_t)(c * g.nw + k) << (2 * LOG2N));
         constexpr int LHB = LOG2H + LOG2B;
         for (int e = tid; e < elems; e += NT) {
             const int jb = e >> LHB;
             const int rem = e & ((1 << LHB) - 1);
-            const int lr = rem >> LOG2B, c = rem & (B - 1);
-            const int jp = (((jb << LOG2B) + c) + (n >> 1)) & nmask;
-            dst[(((size_t)jb << LOG2N) + pp0 + lr) * B + c] = lds[lds_pad((lr << LOG2N) + jp)];
+            const int lr = rem >> LOG2B, col = rem & (B - 1);
+            const int jp = (((jb << LOG2B) + col) + (n >> 1)) & nmask;
+            dst[(((size_t)jb << LOG2N) + pp0 + lr) * B + col] = lds[lds_pad((lr << LOG2N) + jp)];
         }
     } else {
-        C* dst = out + ((size_t)k << (2 * LOG2N)) + ((size_t)row0 << LOG2N);
+        C* dst = out + ((size_t)(c * g.nw + k) << (2 * LOG2N)) + ((size_t)row0 << LOG2N);
         for (int e = tid; e < elems; e += NT) {
             const double2 a = acc[lds_pad(e)];
             dst[e] = cmake<C>((R)a.x, (R)a.y);
@@ -552,7 +591,8 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int k, int s, unsigned
     }
 }
 
-// The gridding step alone: one work-group per strip of every plane; empty strips are zeroed.
+// The gridding step alone: work-group (b, c) = strip b of every plane of channel c; empty
+// strips are zeroed.
 template <typename R, int LOG2N>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
 k_grid_only(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restrict__ occ,
@@ -561,41 +601,44 @@ k_grid_only(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int b = blockIdx.x;
+    const int c = blockIdx.y, b = blockIdx.x;
     const int k = b / g.S, s = b - k * g.S;
-    if (!occ[b]) {
-        C* dst = out + ((size_t)k << (2 * LOG2N)) + ((size_t)(s * SH::H) << LOG2N);
+    if (!occ[c * g.nb1 + b]) {
+        C* dst = out + ((size_t)(c * g.nw + k) << (2 * LOG2N)) + ((size_t)(s * SH::H) << LOG2N);
         for (int e = threadIdx.x; e < SH::H * SH::N; e += SH::NT1) dst[e] = cmake<C>((R)0, (R)0);
         return;
     }
-    grid_strip<R, false, LOG2N>(g, k, s, smem_raw, offsets, rec_cell, rec, kbc, nullptr, out);
+    grid_strip<R, false, LOG2N>(g, c, k, s, smem_raw, offsets, rec_cell, rec, kbc, nullptr, out);
 }
 
-// Gridding + row FFT: a persistent grid walks the work list of occupied strips (heavy ones
-// first) through an atomic counter; every work-group leaves once the list is exhausted.
+// Gridding + row FFT: a persistent grid walks the work list of occupied strips of all
+// channels (heavy ones first) through an atomic counter; every work-group leaves once the
+// list is exhausted.
 template <typename R, int LOG2N>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
-k_grid_rows(Geom g, int nb, Scalars* __restrict__ sc, const uint32_t* __restrict__ list,
+k_grid_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
             const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
             const void* __restrict__ rec, const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
             typename Cx<R>::T* __restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item;
-    const unsigned n_heavy = sc->n_heavy, n_light = sc->n_light;
+    const int total = nch * g.nb1;
+    const unsigned n_heavy = wl->n_heavy, n_light = wl->n_light;
     while (true) {
         if (threadIdx.x == 0) {
-            const unsigned i = atomicAdd(&sc->work_next, 1u);
+            const unsigned i = atomicAdd(&wl->next, 1u);
             int b = -1;
             if (i < n_heavy) b = (int)list[i];
-            else if (i - n_heavy < n_light) b = (int)list[nb - 1 - (int)(i - n_heavy)];
+            else if (i - n_heavy < n_light) b = (int)list[total - 1 - (int)(i - n_heavy)];
             item = b;
         }
         __syncthreads();
         const int b = item;
         __syncthreads();
         if (b < 0) break;
-        const int k = b / g.S, s = b - k * g.S;
-        grid_strip<R, true, LOG2N>(g, k, s, smem_raw, offsets, rec_cell, rec, kbc, opaque_ptr(tw), out);
+        const int c = b / g.nb1, bb = b - c * g.nb1;
+        const int k = bb / g.S, s = bb - k * g.S;
+        grid_strip<R, true, LOG2N>(g, c, k, s, smem_raw, offsets, rec_cell, rec, kbc, opaque_ptr(tw), out);
         __syncthreads();
     }
 }
@@ -651,9 +694,12 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     double* nm1s = reinterpret_cast<double*>(lds + SH::LDS2);
     double nm1r[SH::NM1_LDS ? 1 : E];
     nm1r[0] = 0.0;
-    const int jb = blockIdx.x;
+    const int jb = blockIdx.x, c = blockIdx.y;
     const int tid = threadIdx.x;
     const bool first_active = tid < (elems >> kLogRadix);
+    const uint8_t* pocc = plane_occ + (size_t)c * g.nw;
+    const uint8_t* socc = occ + (size_t)c * g.nb1;
+    const typename Cx<R>::T* cin = inter + ((size_t)c * g.nw << (2 * LOG2N));
 
     // comp is the Kahan compensation (float only)
     R acc[E], comp[sizeof(R) == 4 ? E : 1];
@@ -662,10 +708,10 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     for (int s = 0; s < E; ++s) {
         acc[s] = (R)0;
         if constexpr (sizeof(R) == 4) comp[s] = (R)0;
-        int c, ip;
+        int col, ip;
         double v = 0.0;
-        if (last_slot<LOG2N, kLogRadix, B, NT>(tid, s, c, ip)) {
-            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + c;
+        if (last_slot<LOG2N, kLogRadix, B, NT>(tid, s, col, ip)) {
+            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
             const double l = (double)(j - hn) * g.pixel, m = (double)(i - hn) * g.pixel;
             const double r2 = m * m + l * l;
             v = -r2 / (1.0 + sqrt(1.0 - r2));
@@ -673,29 +719,29 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         if constexpr (SH::NM1_LDS) nm1s[s * NT + tid] = v;
         else nm1r[s] = v;
     }
-    const double w_lo = sc->w_lo, dw = sc->dw, sum_w = sc->sum_w;
+    const double w_lo = sc[c].w_lo, dw = sc[c].dw, sum_w = sc[c].sum_w;
 
     int k = 0;
-    while (k < g.nw && !plane_occ[k]) ++k;
+    while (k < g.nw && !pocc[k]) ++k;
     C x[E], pf[E];
     if (k < g.nw)
-        pass2_load<R, LOG2N, B>(inter + ((size_t)k << (2 * LOG2N)) + (size_t)jb * elems,
-                                occ + (size_t)k * g.S, tid, first_active, g.log2H, pf);
+        pass2_load<R, LOG2N, B>(cin + ((size_t)k << (2 * LOG2N)) + (size_t)jb * elems,
+                                socc + (size_t)k * g.S, tid, first_active, g.log2H, pf);
     while (k < g.nw) {
         int kn = k + 1;
-        while (kn < g.nw && !plane_occ[kn]) ++kn;
+        while (kn < g.nw && !pocc[kn]) ++kn;
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = pf[m];
         if constexpr (Pass2Prefetch<R>::value) {
             if (kn < g.nw)
-                pass2_load<R, LOG2N, B>(inter + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
-                                        occ + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
+                pass2_load<R, LOG2N, B>(cin + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
+                                        socc + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
         }
         // first pass: radix 8 with L = 1 (no twiddles), registers to LDS
         if (first_active) {
             dft8(x);
-            const int c = tid % B, b = tid / B;
-            const int base = (c << LOG2N) + (b << kLogRadix);
+            const int col = tid % B, b = tid / B;
+            const int base = (col << LOG2N) + (b << kLogRadix);
 #pragma unroll
             for (int m = 0; m < E; ++m) lds[lds_pad(base + m)] = x[m];
         }
@@ -733,8 +779,8 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         }
         if constexpr (!Pass2Prefetch<R>::value) {
             if (kn < g.nw)
-                pass2_load<R, LOG2N, B>(inter + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
-                                        occ + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
+                pass2_load<R, LOG2N, B>(cin + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
+                                        socc + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
         }
         __syncthreads();
         k = kn;
@@ -743,10 +789,11 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     const R inv_sw = sum_w > 0.0 ? (R)(1.0 / sum_w) : (R)0;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-        int c, ip;
-        if (last_slot<LOG2N, kLogRadix, B, NT>(tid, s, c, ip)) {
-            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + c;
-            image[(size_t)i * n + j] = sum_w > 0.0 ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
+        int col, ip;
+        if (last_slot<LOG2N, kLogRadix, B, NT>(tid, s, col, ip)) {
+            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
+            image[((size_t)c << (2 * LOG2N)) + (size_t)i * n + j] =
+                sum_w > 0.0 ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
         }
     }
 }

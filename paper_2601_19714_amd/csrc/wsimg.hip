@@ -46,16 +46,23 @@ struct wsimg_plan {
     wsimg_params p{};
     int device = 0;
     hipStream_t stream = nullptr;
-    int64_t max_vis = 0;
+    int64_t max_vis = 0;          // rows per call, all channels together
+    int max_channels = 1;
     Geom g{};
     int nt1 = 0, nt2 = 0;          // threads of the gridding and stacking work-groups
     size_t lds1 = 0, lds2 = 0;     // their dynamic LDS bytes
-    int64_t nb = 0;                // buckets
+    int64_t nb = 0;                // buckets per channel
     size_t cbytes = 0, rbytes = 0; // complex / real element bytes
-    int nparts = 1024;             // reduction partials
-    // device memory
+    // device memory (per-channel arrays hold max_channels entries)
     Partial* partials = nullptr;
     Scalars* scalars = nullptr;
+    WorkList* worklist = nullptr;
+    int64_t* row_off = nullptr;    // channel table: [max_channels + 1] row offsets, then
+    double* freq = nullptr;        // [max_channels] frequencies
+    // pinned host staging of the channel table; staged_ev marks when the device has copied it
+    void* staging = nullptr;
+    hipEvent_t staged_ev = nullptr;
+    bool staged_pending = false;
     uint32_t *counts = nullptr, *offsets = nullptr, *tile_sums = nullptr;
     uint8_t *occ = nullptr, *plane_occ = nullptr;
     uint32_t* list = nullptr;      // work list of occupied strips
@@ -93,11 +100,21 @@ wsimg_status dev_alloc(wsimg_plan* pl, void** out, size_t bytes, const char* wha
 void release(wsimg_plan* pl) {
     for (void* a : pl->allocations) (void)hipFree(a);
     pl->allocations.clear();
+    if (pl->staging) (void)hipHostFree(pl->staging);
+    pl->staging = nullptr;
+    if (pl->staged_ev) (void)hipEventDestroy(pl->staged_ev);
+    pl->staged_ev = nullptr;
     for (auto& ev : pl->pending) for (auto e : ev) (void)hipEventDestroy(e);
     for (auto& ev : pl->spare) for (auto e : ev) (void)hipEventDestroy(e);
     pl->pending.clear();
     pl->spare.clear();
 }
+
+// Reduction partials per channel for a call of nch channels (about 4096 blocks in all).
+int parts_target(int nch) { return std::min(1024, std::max(16, 4096 / std::max(nch, 1))); }
+
+constexpr int kMaxChannels = 65535;                 // the channel is a grid y index
+constexpr int64_t kMaxBucketsTotal = int64_t(1) << 25;   // channels x buckets (x 64 counters)
 
 wsimg_status validate_params(const wsimg_params* p, int64_t max_vis) {
     if (!p) return fail(WSIMG_E_INVALID, "params is NULL");
@@ -177,17 +194,16 @@ wsimg_status configure_shape(wsimg_plan* pl) {
     } while (0)
 
 template <typename R, int LOG2N>
-wsimg_status launch_grid_rows(wsimg_plan* pl, bool fft, void* out) {
+wsimg_status launch_grid_rows(wsimg_plan* pl, int nch, bool fft, void* out) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
     if (fft) {
         hipLaunchKernelGGL((k_grid_rows<R, LOG2N>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1), pl->lds1,
-                           pl->stream, g, (int)pl->nb, pl->scalars, pl->list, pl->offsets, pl->rec_cell,
-                           (const void*)pl->rec, (const R*)pl->kbc, (const C*)pl->tw,
-                           (C*)out);
+                           pl->stream, g, nch, pl->worklist, pl->list, pl->offsets, pl->rec_cell,
+                           (const void*)pl->rec, (const R*)pl->kbc, (const C*)pl->tw, (C*)out);
     } else {
-        hipLaunchKernelGGL((k_grid_only<R, LOG2N>), dim3((unsigned)(g.nw * g.S)), dim3(pl->nt1), pl->lds1,
-                           pl->stream, g, pl->offsets, pl->occ, pl->rec_cell, (const void*)pl->rec,
+        hipLaunchKernelGGL((k_grid_only<R, LOG2N>), dim3((unsigned)(g.nw * g.S), (unsigned)nch), dim3(pl->nt1),
+                           pl->lds1, pl->stream, g, pl->offsets, pl->occ, pl->rec_cell, (const void*)pl->rec,
                            (const R*)pl->kbc, (C*)out);
     }
     WS_LAUNCH_CHECK("grid_rows");
@@ -195,10 +211,11 @@ wsimg_status launch_grid_rows(wsimg_plan* pl, bool fft, void* out) {
 }
 
 template <typename R, int LOG2N>
-wsimg_status launch_cols(wsimg_plan* pl, void* image) {
+wsimg_status launch_cols(wsimg_plan* pl, int nch, void* image) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
-    hipLaunchKernelGGL((k_cols_stack<R, LOG2N>), dim3((unsigned)g.NB), dim3(pl->nt2), pl->lds2, pl->stream, g,
+    hipLaunchKernelGGL((k_cols_stack<R, LOG2N>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2), pl->lds2,
+                       pl->stream, g,
                        pl->scalars, pl->occ, pl->plane_occ, (const C*)pl->inter, (const C*)pl->tw,
                        (const R*)pl->inv_taper, (R*)image);
     WS_LAUNCH_CHECK("cols_stack");
@@ -222,21 +239,58 @@ wsimg_status launch_cols(wsimg_plan* pl, void* image) {
     }
 
 template <typename R> wsimg_status configure(wsimg_plan* pl) { WS_SIZE_DISPATCH(R, pl->g.log2n, configure_shape, pl) }
-template <typename R> wsimg_status grid_rows(wsimg_plan* pl, bool fft, void* out) {
-    WS_SIZE_DISPATCH(R, pl->g.log2n, launch_grid_rows, pl, fft, out)
+template <typename R> wsimg_status grid_rows(wsimg_plan* pl, int nch, bool fft, void* out) {
+    WS_SIZE_DISPATCH(R, pl->g.log2n, launch_grid_rows, pl, nch, fft, out)
 }
-template <typename R> wsimg_status cols_stack(wsimg_plan* pl, void* image) {
-    WS_SIZE_DISPATCH(R, pl->g.log2n, launch_cols, pl, image)
+template <typename R> wsimg_status cols_stack(wsimg_plan* pl, int nch, void* image) {
+    WS_SIZE_DISPATCH(R, pl->g.log2n, launch_cols, pl, nch, image)
 }
 
-wsimg_status validate_call(wsimg_plan* pl, int64_t n_vis, const double* uvw, const void* vis,
-                           const void* weights, double freq_hz, void* out) {
+// A call's channels: counts and frequencies as passed (host), with their totals.
+struct Batch {
+    int nch = 0;
+    const int64_t* counts = nullptr;
+    const double* freqs = nullptr;
+    int64_t total = 0, max_count = 0;
+};
+
+wsimg_status validate_call(wsimg_plan* pl, int nch, const int64_t* counts, const double* freqs,
+                           const double* uvw, const void* vis, const void* weights, void* out, Batch& bt) {
     if (!pl) return fail(WSIMG_E_INVALID, "plan is NULL");
-    if (n_vis < 0) return fail(WSIMG_E_INVALID, "n_vis < 0");
-    if (n_vis > pl->max_vis) return fail(WSIMG_E_CAPACITY, "n_vis exceeds the plan's max_vis");
-    if (n_vis > 0 && (!uvw || !vis || !weights)) return fail(WSIMG_E_INVALID, "input pointer is NULL");
+    if (nch < 1 || nch > pl->max_channels)
+        return fail(WSIMG_E_INVALID, "n_channels must be in [1, the plan's max_channels]");
+    if (!counts || !freqs) return fail(WSIMG_E_INVALID, "row_counts or freqs_hz is NULL");
+    int64_t total = 0, mx = 0;
+    for (int c = 0; c < nch; ++c) {
+        if (counts[c] < 0) return fail(WSIMG_E_INVALID, "n_vis < 0");
+        if (counts[c] > pl->max_vis || total > pl->max_vis - counts[c])
+            return fail(WSIMG_E_CAPACITY, "n_vis exceeds the plan's max_vis");
+        total += counts[c];
+        mx = std::max(mx, counts[c]);
+        if (!(freqs[c] > 0.0) || !std::isfinite(freqs[c]))
+            return fail(WSIMG_E_INVALID, "freq_hz must be finite and > 0");
+    }
+    if (total > 0 && (!uvw || !vis || !weights)) return fail(WSIMG_E_INVALID, "input pointer is NULL");
     if (!out) return fail(WSIMG_E_INVALID, "output pointer is NULL");
-    if (!(freq_hz > 0.0) || !std::isfinite(freq_hz)) return fail(WSIMG_E_INVALID, "freq_hz must be finite and > 0");
+    bt.nch = nch; bt.counts = counts; bt.freqs = freqs; bt.total = total; bt.max_count = mx;
+    return WSIMG_OK;
+}
+
+// Channel table -> pinned staging -> device, on the plan's stream.  The staging buffer is
+// rewritten only after the device has copied the previous call's table.
+wsimg_status upload_channels(wsimg_plan* pl, const Batch& bt) {
+    if (pl->staged_pending) {
+        WS_HIP(hipEventSynchronize(pl->staged_ev));
+        pl->staged_pending = false;
+    }
+    int64_t* ro = static_cast<int64_t*>(pl->staging);
+    double* fq = reinterpret_cast<double*>(ro + (pl->max_channels + 1));
+    ro[0] = 0;
+    for (int c = 0; c < bt.nch; ++c) { ro[c + 1] = ro[c] + bt.counts[c]; fq[c] = bt.freqs[c]; }
+    WS_HIP(hipMemcpyAsync(pl->row_off, ro, sizeof(int64_t) * (bt.nch + 1), hipMemcpyHostToDevice, pl->stream));
+    WS_HIP(hipMemcpyAsync(pl->freq, fq, sizeof(double) * bt.nch, hipMemcpyHostToDevice, pl->stream));
+    WS_HIP(hipEventRecord(pl->staged_ev, pl->stream));
+    pl->staged_pending = true;
     return WSIMG_OK;
 }
 
@@ -266,34 +320,39 @@ inline unsigned blocks_for(int64_t count, int threads) {
     return (unsigned)((count + threads - 1) / threads);
 }
 
-// Stages shared by wsimg_image and wsimg_grid: counters, plane range, bucket sort.
+// Stages shared by wsimg_image and wsimg_grid: counters, plane ranges, bucket sort.
 template <typename R>
-wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, const void* vis,
-                      const void* wts, double freq) {
+wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* uvw, const void* vis,
+                      const void* wts) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
     hipStream_t s = pl->stream;
-    const int64_t nbk = pl->nb;
+    const int nch = bt.nch;
+    const int64_t nbk = pl->nb * nch;
     const int64_t ncnt = nbk * kReplicas;
+    const Chan ch{pl->row_off, pl->freq};
+    if (auto r = upload_channels(pl, bt)) return r;
     hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(blocks_for(ncnt, 256), 8192)), dim3(256), 0, s,
                        pl->counts, ncnt, 0u);
     WS_LAUNCH_CHECK("fill");
     if (auto r = st.after(0)) return r;
 
-    const int64_t chunk = std::max<int64_t>(1, (M + pl->nparts - 1) / pl->nparts);
+    const int64_t M = bt.max_count;
+    const int64_t chunk = std::max<int64_t>(1, (M + parts_target(nch) - 1) / parts_target(nch));
     const int nparts = M > 0 ? (int)((M + chunk - 1) / chunk) : 0;
     if (nparts > 0) {
-        hipLaunchKernelGGL((k_reduce<R>), dim3(nparts), dim3(256), 0, s, M, chunk, uvw,
-                           (const R*)wts, freq, g, pl->partials);
+        hipLaunchKernelGGL((k_reduce<R>), dim3(nparts, nch), dim3(256), 0, s, ch, chunk, nparts, uvw,
+                           (const R*)wts, g, pl->partials);
         WS_LAUNCH_CHECK("reduce");
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, nparts, pl->partials, g, M, pl->scalars);
+    hipLaunchKernelGGL(k_finalize, dim3(nch), dim3(256), 0, s, nparts, pl->partials, g, ch, pl->scalars,
+                       pl->worklist);
     WS_LAUNCH_CHECK("finalize");
     if (auto r = st.after(1)) return r;
 
     if (M > 0) {
-        hipLaunchKernelGGL((k_key<R>), dim3(blocks_for(M, 256)), dim3(256), 0, s, M, uvw, (const R*)wts,
-                           freq, g, pl->scalars, pl->key, pl->rank, pl->counts);
+        hipLaunchKernelGGL((k_key<R>), dim3(blocks_for(M, 256), nch), dim3(256), 0, s, ch, uvw, (const R*)wts,
+                           g, pl->scalars, pl->key, pl->rank, pl->counts);
         WS_LAUNCH_CHECK("key");
     }
     if (auto r = st.after(2)) return r;
@@ -305,14 +364,14 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, c
     WS_LAUNCH_CHECK("scan_top");
     hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(256), 0, s, ncnt, pl->counts, pl->tile_sums, pl->offsets);
     WS_LAUNCH_CHECK("scan_down");
-    hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nbk, 256)), dim3(256), 0, s, (int)nbk, pl->offsets, g,
-                       pl->occ, pl->plane_occ, pl->list, pl->scalars);
+    hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nbk, 256)), dim3(256), 0, s, nch, pl->offsets, g,
+                       pl->occ, pl->plane_occ, pl->list, pl->scalars, pl->worklist);
     WS_LAUNCH_CHECK("occupancy");
     if (auto r = st.after(3)) return r;
 
     if (M > 0) {
-        hipLaunchKernelGGL((k_scatter<R, R>), dim3(blocks_for(M, 256)), dim3(256), 0, s, M, uvw,
-                           (const C*)vis, (const R*)wts, freq, g, pl->key, pl->rank, pl->offsets,
+        hipLaunchKernelGGL((k_scatter<R, R>), dim3(blocks_for(M, 256), nch), dim3(256), 0, s, ch, uvw,
+                           (const C*)vis, (const R*)wts, g, pl->key, pl->rank, pl->offsets,
                            pl->rec_cell, pl->rec);
         WS_LAUNCH_CHECK("scatter");
     }
@@ -321,50 +380,147 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, int64_t M, const double* uvw, c
 }
 
 template <typename R>
-wsimg_status run_image(wsimg_plan* pl, int64_t M, const double* uvw, const void* vis, const void* wts,
-                       double freq, void* image, bool grid_only) {
+wsimg_status run_image(wsimg_plan* pl, const Batch& bt, const double* uvw, const void* vis, const void* wts,
+                       void* image, bool grid_only) {
     Stamp st(pl);
     if (auto r = st.begin()) return r;
-    if (auto r = run_sort<R>(pl, st, M, uvw, vis, wts, freq)) return r;
+    if (auto r = run_sort<R>(pl, st, bt, uvw, vis, wts)) return r;
     if (grid_only) {
-        if (auto r = grid_rows<R>(pl, false, image)) return r;
+        if (auto r = grid_rows<R>(pl, bt.nch, false, image)) return r;
         if (auto r = st.after(5)) return r;
         if (auto r = st.after(6)) return r;
         return WSIMG_OK;
     }
-    if (auto r = grid_rows<R>(pl, true, pl->inter)) return r;
+    if (auto r = grid_rows<R>(pl, bt.nch, true, pl->inter)) return r;
     if (auto r = st.after(5)) return r;
-    if (auto r = cols_stack<R>(pl, image)) return r;
+    if (auto r = cols_stack<R>(pl, bt.nch, image)) return r;
     if (auto r = st.after(6)) return r;
     return WSIMG_OK;
 }
 
-wsimg_status finish_call(wsimg_plan* pl, wsimg_stats* stats) {
+wsimg_status finish_call(wsimg_plan* pl, int nch, wsimg_stats* stats) {
     if (!stats) return WSIMG_OK;
-    Scalars h{};
-    WS_HIP(hipMemcpyAsync(&h, pl->scalars, sizeof h, hipMemcpyDeviceToHost, pl->stream));
+    std::vector<Scalars> h((size_t)nch);
+    WS_HIP(hipMemcpyAsync(h.data(), pl->scalars, sizeof(Scalars) * nch, hipMemcpyDeviceToHost, pl->stream));
     WS_HIP(hipStreamSynchronize(pl->stream));
-    stats->n_in = (int64_t)h.n_in;
-    stats->n_gridded = (int64_t)h.n_kept;
-    stats->n_dropped = (int64_t)(h.n_in - h.n_kept);
-    stats->sum_w = h.sum_w;
-    stats->w_lo = h.w_lo;
-    stats->w_hi = h.w_hi;
-    stats->n_strips_occupied = (int64_t)h.n_occ;
-    stats->n_planes_occupied = (int64_t)h.n_planes;
-    if (!(h.sum_w != 0.0)) return fail(WSIMG_E_EMPTY, "the kept visibilities have zero total weight");
+    bool empty = false;
+    for (int c = 0; c < nch; ++c) {
+        wsimg_stats& o = stats[c];
+        o.n_in = (int64_t)h[c].n_in;
+        o.n_gridded = (int64_t)h[c].n_kept;
+        o.n_dropped = (int64_t)(h[c].n_in - h[c].n_kept);
+        o.sum_w = h[c].sum_w;
+        o.w_lo = h[c].w_lo;
+        o.w_hi = h[c].w_hi;
+        o.n_strips_occupied = (int64_t)h[c].n_occ;
+        o.n_planes_occupied = (int64_t)h[c].n_planes;
+        if (!(h[c].sum_w != 0.0)) empty = true;
+    }
+    if (empty) return fail(WSIMG_E_EMPTY, "the kept visibilities of a channel have zero total weight");
     return WSIMG_OK;
 }
 
-wsimg_status dispatch(wsimg_plan* pl, int64_t n_vis, const double* uvw, const void* vis, const void* wts,
-                      double freq, void* out, wsimg_stats* stats, bool grid_only) {
-    if (auto r = validate_call(pl, n_vis, uvw, vis, wts, freq, out)) return r;
+wsimg_status dispatch(wsimg_plan* pl, int nch, const int64_t* counts, const double* uvw, const void* vis,
+                      const void* wts, const double* freqs, void* out, wsimg_stats* stats, bool grid_only) {
+    Batch bt;
+    if (auto r = validate_call(pl, nch, counts, freqs, uvw, vis, wts, out, bt)) return r;
     WS_HIP(hipSetDevice(pl->device));
     wsimg_status r = pl->p.precision == WSIMG_F32
-                         ? run_image<float>(pl, n_vis, uvw, vis, wts, freq, out, grid_only)
-                         : run_image<double>(pl, n_vis, uvw, vis, wts, freq, out, grid_only);
+                         ? run_image<float>(pl, bt, uvw, vis, wts, out, grid_only)
+                         : run_image<double>(pl, bt, uvw, vis, wts, out, grid_only);
     if (r) return r;
-    return finish_call(pl, stats);
+    return finish_call(pl, nch, stats);
+}
+
+wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, int max_channels,
+                    void* hip_stream) {
+    if (!out) return fail(WSIMG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (auto r = validate_params(p, max_vis)) return r;
+    if (max_channels < 1 || max_channels > kMaxChannels)
+        return fail(WSIMG_E_INVALID, "max_channels must be in [1, 65535]");
+
+    wsimg_plan* pl = new (std::nothrow) wsimg_plan();
+    if (!pl) return fail(WSIMG_E_NOMEM, "host allocation of the plan failed");
+    pl->p = *p;
+    if (!(pl->p.beta > 0.0)) pl->p.beta = 2.34 * pl->p.support;
+    pl->max_vis = max_vis;
+    pl->max_channels = max_channels;
+    pl->stream = (hipStream_t)hip_stream;
+
+    const bool f32 = p->precision == WSIMG_F32;
+    pl->rbytes = f32 ? 4 : 8;
+    pl->cbytes = 2 * pl->rbytes;
+    const int n = p->n;
+    Geom& g = pl->g;
+    g.n = n; g.log2n = ilog2(n); g.nw = p->n_wplanes; g.support = p->support; g.half = (p->support - 1) / 2;
+    g.du = 1.0 / ((double)n * p->pixel_rad);
+    g.half_n = (double)n / 2.0;
+    g.pixel = p->pixel_rad;
+    g.fixed_range = (p->flags & WSIMG_FIXED_WRANGE) ? 1 : 0;
+    g.w_lo_fixed = p->w_lo; g.w_hi_fixed = p->w_hi;
+    {
+        wsimg_status rs = f32 ? configure<float>(pl) : configure<double>(pl);
+        if (rs) { delete pl; return rs; }
+    }
+    pl->nb = (int64_t)g.nw * g.S;
+    g.nb1 = (int)pl->nb;
+    if (pl->nb * max_channels > kMaxBucketsTotal) {
+        delete pl;
+        return fail(WSIMG_E_UNSUPPORTED, "max_channels x n_wplanes x strips exceeds 2^25 sort buckets");
+    }
+
+    hipError_t he = hipGetDevice(&pl->device);
+    if (he != hipSuccess) { delete pl; return fail(WSIMG_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he)); }
+    int cus = 0;
+    he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device);
+    if (he != hipSuccess || cus <= 0) { delete pl; return fail(WSIMG_E_HIP, "hipDeviceGetAttribute(CU count) failed"); }
+    // as many strip work-groups as fit at once: one per CU while the LDS strip exceeds 80 KB
+    pl->persist_blocks = cus * std::max(1, (int)((160 * 1024) / std::max<size_t>(pl->lds1, 1)));
+
+    wsimg_status r = WSIMG_OK;
+    const size_t mv = (size_t)std::max<int64_t>(max_vis, 1);
+    const size_t mc = (size_t)max_channels;
+    const size_t cells = (size_t)g.nw * (size_t)n * (size_t)n;
+    const size_t nbt = (size_t)pl->nb * mc;
+    size_t nparts_alloc = 0;
+    for (int c = 1; c <= max_channels; ++c) nparts_alloc = std::max(nparts_alloc, (size_t)c * parts_target(c));
+    void* tmp = nullptr;
+#define ALLOC(field, bytes, name)                                                  \
+    if (!r) { r = dev_alloc(pl, &tmp, (bytes), name); pl->field = (decltype(pl->field))tmp; }
+    ALLOC(partials, sizeof(Partial) * nparts_alloc, "partials");
+    ALLOC(scalars, sizeof(Scalars) * mc, "scalars");
+    ALLOC(worklist, sizeof(WorkList), "work list counters");
+    ALLOC(row_off, sizeof(int64_t) * (mc + 1), "channel row offsets");
+    ALLOC(freq, sizeof(double) * mc, "channel frequencies");
+    ALLOC(counts, sizeof(uint32_t) * nbt * kReplicas, "counts");
+    ALLOC(offsets, sizeof(uint32_t) * (nbt * kReplicas + 1), "offsets");
+    ALLOC(tile_sums, sizeof(uint32_t) * ((nbt * kReplicas + kScanTile - 1) / kScanTile), "scan tiles");
+    ALLOC(occ, nbt, "occupancy");
+    ALLOC(list, sizeof(uint32_t) * nbt, "strip work list");
+    ALLOC(plane_occ, (size_t)g.nw * mc, "plane occupancy");
+    ALLOC(key, sizeof(uint32_t) * mv, "keys");
+    ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
+    ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * mv, "record cells");
+    ALLOC(rec, (f32 ? 16 : 32) * mv, "records");
+    ALLOC(inter, pl->cbytes * cells * mc, "row-transformed planes");
+    ALLOC(tw, pl->cbytes * n, "twiddles");
+    ALLOC(inv_taper, pl->rbytes * n, "taper");
+    ALLOC(kbc, pl->rbytes * (size_t)p->support * 17, "kernel polynomials");
+#undef ALLOC
+    if (!r) {
+        hipError_t e = hipHostMalloc(&pl->staging, sizeof(int64_t) * (mc + 1) + sizeof(double) * mc,
+                                     hipHostMallocDefault);
+        if (e != hipSuccess) { pl->staging = nullptr; r = fail(WSIMG_E_NOMEM, "hipHostMalloc(channel table) failed"); }
+    }
+    if (!r) {
+        hipError_t e = hipEventCreateWithFlags(&pl->staged_ev, hipEventDisableTiming);
+        if (e != hipSuccess) { pl->staged_ev = nullptr; r = fail(WSIMG_E_HIP, "hipEventCreate failed"); }
+    }
+    if (!r) r = f32 ? upload_tables<float>(pl) : upload_tables<double>(pl);
+    if (r) { release(pl); delete pl; return r; }
+    *out = pl;
+    return WSIMG_OK;
 }
 
 }  // namespace
@@ -393,69 +549,12 @@ const char* wsimg_stage_name(int32_t stage) {
 }
 
 wsimg_status wsimg_plan_create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, void* hip_stream) {
-    if (!out) return fail(WSIMG_E_INVALID, "out is NULL");
-    *out = nullptr;
-    if (auto r = validate_params(p, max_vis)) return r;
+    return create(out, p, max_vis, 1, hip_stream);
+}
 
-    wsimg_plan* pl = new (std::nothrow) wsimg_plan();
-    if (!pl) return fail(WSIMG_E_NOMEM, "host allocation of the plan failed");
-    pl->p = *p;
-    if (!(pl->p.beta > 0.0)) pl->p.beta = 2.34 * pl->p.support;
-    pl->max_vis = max_vis;
-    pl->stream = (hipStream_t)hip_stream;
-
-    const bool f32 = p->precision == WSIMG_F32;
-    pl->rbytes = f32 ? 4 : 8;
-    pl->cbytes = 2 * pl->rbytes;
-    const int n = p->n;
-    Geom& g = pl->g;
-    g.n = n; g.log2n = ilog2(n); g.nw = p->n_wplanes; g.support = p->support; g.half = (p->support - 1) / 2;
-    g.du = 1.0 / ((double)n * p->pixel_rad);
-    g.half_n = (double)n / 2.0;
-    g.pixel = p->pixel_rad;
-    g.fixed_range = (p->flags & WSIMG_FIXED_WRANGE) ? 1 : 0;
-    g.w_lo_fixed = p->w_lo; g.w_hi_fixed = p->w_hi;
-    {
-        wsimg_status rs = f32 ? configure<float>(pl) : configure<double>(pl);
-        if (rs) { delete pl; return rs; }
-    }
-    pl->nb = (int64_t)g.nw * g.S;
-
-    hipError_t he = hipGetDevice(&pl->device);
-    if (he != hipSuccess) { delete pl; return fail(WSIMG_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he)); }
-    int cus = 0;
-    he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device);
-    if (he != hipSuccess || cus <= 0) { delete pl; return fail(WSIMG_E_HIP, "hipDeviceGetAttribute(CU count) failed"); }
-    // as many strip work-groups as fit at once: one per CU while the LDS strip exceeds 80 KB
-    pl->persist_blocks = cus * std::max(1, (int)((160 * 1024) / std::max<size_t>(pl->lds1, 1)));
-
-    wsimg_status r = WSIMG_OK;
-    const size_t mv = (size_t)std::max<int64_t>(max_vis, 1);
-    const size_t cells = (size_t)g.nw * (size_t)n * (size_t)n;
-    void* tmp = nullptr;
-#define ALLOC(field, bytes, name)                                                  \
-    if (!r) { r = dev_alloc(pl, &tmp, (bytes), name); pl->field = (decltype(pl->field))tmp; }
-    ALLOC(partials, sizeof(Partial) * pl->nparts, "partials");
-    ALLOC(scalars, sizeof(Scalars), "scalars");
-    ALLOC(counts, sizeof(uint32_t) * pl->nb * kReplicas, "counts");
-    ALLOC(offsets, sizeof(uint32_t) * (pl->nb * kReplicas + 1), "offsets");
-    ALLOC(tile_sums, sizeof(uint32_t) * ((pl->nb * kReplicas + kScanTile - 1) / kScanTile), "scan tiles");
-    ALLOC(occ, (size_t)pl->nb, "occupancy");
-    ALLOC(list, sizeof(uint32_t) * (size_t)pl->nb, "strip work list");
-    ALLOC(plane_occ, (size_t)g.nw, "plane occupancy");
-    ALLOC(key, sizeof(uint32_t) * mv, "keys");
-    ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
-    ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * mv, "record cells");
-    ALLOC(rec, (f32 ? 16 : 32) * mv, "records");
-    ALLOC(inter, pl->cbytes * cells, "row-transformed planes");
-    ALLOC(tw, pl->cbytes * n, "twiddles");
-    ALLOC(inv_taper, pl->rbytes * n, "taper");
-    ALLOC(kbc, pl->rbytes * (size_t)p->support * 17, "kernel polynomials");
-#undef ALLOC
-    if (!r) r = f32 ? upload_tables<float>(pl) : upload_tables<double>(pl);
-    if (r) { release(pl); delete pl; return r; }
-    *out = pl;
-    return WSIMG_OK;
+wsimg_status wsimg_plan_create_batch(wsimg_plan** out, const wsimg_params* p, int64_t max_vis,
+                                     int32_t max_channels, void* hip_stream) {
+    return create(out, p, max_vis, max_channels, hip_stream);
 }
 
 wsimg_status wsimg_plan_destroy(wsimg_plan* plan) {
@@ -484,17 +583,24 @@ wsimg_status wsimg_plan_get_info(const wsimg_plan* plan, wsimg_plan_info* info) 
     info->n_buckets = plan->nb;
     info->max_vis = plan->max_vis;
     info->device_bytes = plan->device_bytes;
+    info->max_channels = plan->max_channels;
     return WSIMG_OK;
 }
 
 wsimg_status wsimg_image(wsimg_plan* plan, int64_t n_vis, const double* uvw_m, const void* vis,
                          const void* weights, double freq_hz, void* image_out, wsimg_stats* stats) {
-    return dispatch(plan, n_vis, uvw_m, vis, weights, freq_hz, image_out, stats, false);
+    return dispatch(plan, 1, &n_vis, uvw_m, vis, weights, &freq_hz, image_out, stats, false);
+}
+
+wsimg_status wsimg_image_batch(wsimg_plan* plan, int32_t n_channels, const int64_t* row_counts,
+                               const double* uvw_m, const void* vis, const void* weights,
+                               const double* freqs_hz, void* images_out, wsimg_stats* stats) {
+    return dispatch(plan, n_channels, row_counts, uvw_m, vis, weights, freqs_hz, images_out, stats, false);
 }
 
 wsimg_status wsimg_grid(wsimg_plan* plan, int64_t n_vis, const double* uvw_m, const void* vis,
                         const void* weights, double freq_hz, void* grid_out, wsimg_stats* stats) {
-    return dispatch(plan, n_vis, uvw_m, vis, weights, freq_hz, grid_out, stats, true);
+    return dispatch(plan, 1, &n_vis, uvw_m, vis, weights, &freq_hz, grid_out, stats, true);
 }
 
 wsimg_status wsimg_set_timing(wsimg_plan* plan, int32_t enable) {

@@ -14,6 +14,7 @@ from .interferometer import (  # noqa: F401
     config_spec,
     make_config,
     make_channels,
+    stack_channels,
     antenna_layout,
     baselines_xyz,
     uvw_track,

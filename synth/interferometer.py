@@ -330,3 +330,13 @@ def make_channels(device: str = "cpu", n_channels: Optional[int] = None) -> List
                      support=spec["support"], beta=2.34 * spec["support"], sources=src)
         out.append(ds.as_precision("f32"))
     return out
+
+
+def stack_channels(channels: List[Dataset]):
+    """Concatenate channel datasets row-wise: (uvw_m, vis, weights, row_counts, freqs_hz)."""
+    uvw = np.concatenate([c.uvw_m for c in channels], axis=0)
+    vis = np.concatenate([c.vis for c in channels])
+    wts = np.concatenate([c.weights for c in channels])
+    counts = [int(c.uvw_m.shape[0]) for c in channels]
+    freqs = [float(c.freq_hz) for c in channels]
+    return uvw, vis, wts, counts, freqs
