@@ -90,7 +90,7 @@ typedef struct {
     int64_t max_channels;    /* channels one wsimg_image_batch call may image              */
 } wsimg_plan_info;
 
-#define WSIMG_N_KERNELS 7
+#define WSIMG_N_KERNELS 8
 typedef struct {
     int64_t calls;                     /* wsimg_image/wsimg_grid calls timed since enabling   */
     double ms[WSIMG_N_KERNELS];        /* summed device time of each kernel stage             */

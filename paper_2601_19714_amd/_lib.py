@@ -18,7 +18,7 @@ WSIMG_E_UNSUPPORTED = -6
 WSIMG_F32 = 1
 WSIMG_F64 = 2
 WSIMG_FIXED_WRANGE = 0x1
-WSIMG_N_KERNELS = 7
+WSIMG_N_KERNELS = 8
 
 # every symbol include/wsimg.h declares
 EXPORTS = (
@@ -63,6 +63,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2601_19714_amd.build.build()")
+    # torch first: its HIP runtime is then the one the library binds to (device memory and
+    # streams come from torch; two runtimes in one process do not share devices)
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.wsimg_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), i64, vp]

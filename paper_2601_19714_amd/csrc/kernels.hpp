@@ -194,9 +194,16 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
 constexpr int kReplicas = 64;
 constexpr int kLogReplicas = 6;
 
-// Ranks are taken once per distinct key in a wave: the lanes sharing a key elect a leader,
-// which adds their count to the counter; each lane's rank is the returned base plus the
-// number of lower lanes with the same key.
+// Ranks.  With WSIMG_KEY_WAVE_AGG = 1 (default) the lanes of a wave sharing a key elect a
+// leader that adds their count, and each lane's rank is the returned base plus the number of
+// lower lanes with the same key; the grouping uses scalar lane reads and ballots, and the
+// leaders' atomics go out together.  With 0 each lane takes its rank with its own atomic (one
+// instruction per wave, but the lanes hitting a hot bucket serialise in the cache: measured
+// 3.4x slower on 64 channels of 1024^2, where most lanes of a wave share a few buckets).
+#ifndef WSIMG_KEY_WAVE_AGG
+#define WSIMG_KEY_WAVE_AGG 1
+#endif
+
 template <typename WT>
 __global__ void __launch_bounds__(256)
 k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom g,
@@ -217,21 +224,31 @@ k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom 
             kk = (uint32_t)(c * g.nb1 + k * g.S + (p0 >> g.log2H));
         }
     }
+    const uint32_t rep = blockIdx.x & (kReplicas - 1);
+#if WSIMG_KEY_WAVE_AGG
     const int lane = threadIdx.x & 63;
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t rep = blockIdx.x & (kReplicas - 1);
     unsigned long long todo = __ballot(kk != 0xFFFFFFFFu);
-    uint32_t rr = 0;
+    uint32_t rr = 0, group = 0;
+    int my_leader = lane;
     while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const uint32_t lkey = __shfl(kk, leader, 64);
+        const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)todo) - 1);
+        const uint32_t lkey = (uint32_t)__builtin_amdgcn_readlane((int)kk, leader);
         const unsigned long long same = __ballot(kk == lkey);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&counts[((size_t)lkey << kLogReplicas) + rep], (uint32_t)__popcll(same));
-        base = __shfl(base, leader, 64);
-        if (kk == lkey) rr = base + (uint32_t)__popcll(same & below);
+        if (kk == lkey) {
+            my_leader = leader;
+            rr = (uint32_t)__popcll(same & below);
+        }
+        if (lane == leader) group = (uint32_t)__popcll(same);
         todo &= ~same;
     }
+    uint32_t base = 0;
+    if (group) base = atomicAdd(&counts[((size_t)kk << kLogReplicas) + rep], group);
+    rr += __shfl(base, my_leader, 64);
+#else
+    uint32_t rr = 0;
+    if (kk != 0xFFFFFFFFu) rr = atomicAdd(&counts[((size_t)kk << kLogReplicas) + rep], 1u);
+#endif
     if (in) {
         key[m] = kk;
         rank[m] = rr;
@@ -423,14 +440,47 @@ k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __re
     }
 }
 
-// One record: tap origin (q0, p0), sub-cell offsets and W*V in the plan precision.
+// One record as stored.
+template <typename R> struct RawRec;
+template <> struct RawRec<float> { uint4 q; };
+template <> struct RawRec<double> { uint32_t cell; double2 f, v; };
+
 template <typename R>
-__device__ __forceinline__ void load_record(const uint32_t* __restrict__ rec_cell, const void* __restrict__ rec,
-                                            uint32_t r, int strip, int log2H, int& q0, int& p0,
-                                            typename Cx<R>::T& fr, typename Cx<R>::T& v) {
+__device__ __forceinline__ RawRec<R> fetch_record(const uint32_t* __restrict__ rec_cell,
+                                                  const void* __restrict__ rec, uint32_t r) {
+    RawRec<R> x;
+    if constexpr (sizeof(R) == 4) {
+        x.q = reinterpret_cast<const uint4*>(rec)[r];
+    } else {
+        x.cell = rec_cell[r];
+        const double2* r2 = reinterpret_cast<const double2*>(rec);
+        x.f = r2[2 * (size_t)r];
+        x.v = r2[2 * (size_t)r + 1];
+    }
+    return x;
+}
+
+template <typename R>
+__device__ __forceinline__ void store_record(uint32_t* __restrict__ rec_cell, void* __restrict__ rec,
+                                             uint32_t r, const RawRec<R>& x) {
+    if constexpr (sizeof(R) == 4) {
+        reinterpret_cast<uint4*>(rec)[r] = x.q;
+    } else {
+        rec_cell[r] = x.cell;
+        double2* r2 = reinterpret_cast<double2*>(rec);
+        r2[2 * (size_t)r] = x.f;
+        r2[2 * (size_t)r + 1] = x.v;
+    }
+}
+
+// Tap origin (q0, p0), sub-cell offsets and W*V in the plan precision; strip is the strip of
+// the record's bucket (the float record keeps only p0 mod H).
+template <typename R>
+__device__ __forceinline__ void decode_record(const RawRec<R>& x, int strip, int log2H, int& q0, int& p0,
+                                              typename Cx<R>::T& fr, typename Cx<R>::T& v) {
     using C = typename Cx<R>::T;
     if constexpr (sizeof(R) == 4) {
-        const uint4 q = reinterpret_cast<const uint4*>(rec)[r];
+        const uint4 q = x.q;
         q0 = (int)(q.x & 0x1FFFu);
         p0 = (strip << log2H) + (int)((q.x >> 13) & 0x1Fu);
         const uint32_t ux = (q.x >> 18) | ((q.y & 0x1FFu) << 14), uy = q.y >> 9;
@@ -438,44 +488,136 @@ __device__ __forceinline__ void load_record(const uint32_t* __restrict__ rec_cel
         fr = cmake<C>((float)ux * inv - 0.5f, (float)uy * inv - 0.5f);
         v = cmake<C>(__uint_as_float(q.z), __uint_as_float(q.w));
     } else {
-        const uint32_t cell = rec_cell[r];
-        q0 = (int)(cell & 0xFFFFu);
-        p0 = (int)(cell >> 16);
-        const double2* r2 = reinterpret_cast<const double2*>(rec);
-        fr = r2[2 * (size_t)r];
-        v = r2[2 * (size_t)r + 1];
+        q0 = (int)(x.cell & 0xFFFFu);
+        p0 = (int)(x.cell >> 16);
+        fr = x.f;
+        v = x.v;
+    }
+}
+
+// Origin index q0 * H + (p0 mod H) of a stored record (< H * N <= 8192).
+template <typename R>
+__device__ __forceinline__ uint32_t raw_origin(const RawRec<R>& x, int log2H) {
+    if constexpr (sizeof(R) == 4) return ((x.q.x & 0x1FFFu) << log2H) | ((x.q.x >> 13) & 0x1Fu);
+    else return ((x.cell & 0xFFFFu) << log2H) | ((x.cell >> 16) & ((1u << log2H) - 1u));
+}
+
+// ---------------------------------------------------------------------------------------
+// Records of each bucket grouped by tap origin.
+//
+// Inside one bucket (channel, plane, strip) the records are put in order of their tap origin
+// o = q0 * H + (p0 mod H), o < H * N <= 8192, by a counting sort in LDS (one work-group per
+// bucket).  Records with the same origin then lie next to each other, and the gridding sums
+// a run of them in registers before adding it to the strip once: on 8 s integrations a
+// baseline stays in one grid cell for several steps, and dense buckets hold tens of records
+// per origin.
+constexpr int kOriginBins = 8192;
+constexpr int kSortThreads = 512;
+
+// Work-group (x, c) = bucket x of channel c.
+template <typename R>
+__global__ void __launch_bounds__(kSortThreads)
+k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
+              const void* __restrict__ rec, uint32_t* __restrict__ rec_cell2, void* __restrict__ rec2) {
+    __shared__ uint32_t hist[kOriginBins];
+    __shared__ uint32_t part[kSortThreads];
+    constexpr int PER = kOriginBins / kSortThreads;
+    const size_t b = (size_t)blockIdx.y * g.nb1 + blockIdx.x;
+    const uint32_t beg = offsets[b << kLogReplicas], end = offsets[(b + 1) << kLogReplicas];
+    const int t = threadIdx.x;
+    if (end - beg <= 1) {
+        if (end - beg == 1 && t == 0) store_record<R>(rec_cell2, rec2, beg, fetch_record<R>(rec_cell, rec, beg));
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) hist[i * kSortThreads + t] = 0u;
+    __syncthreads();
+    for (uint32_t r = beg + t; r < end; r += kSortThreads)
+        atomicAdd(&hist[raw_origin<R>(fetch_record<R>(rec_cell, rec, r), g.log2H)], 1u);
+    __syncthreads();
+    // exclusive scan of the bins: thread t owns bins [t * PER, (t + 1) * PER)
+    uint32_t v[PER], sum = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) { v[i] = hist[t * PER + i]; sum += v[i]; }
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < kSortThreads; o <<= 1) {
+        const uint32_t x = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = t > 0 ? part[t - 1] : 0u;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) { hist[t * PER + i] = run; run += v[i]; }
+    __syncthreads();
+    for (uint32_t r = beg + t; r < end; r += kSortThreads) {
+        const RawRec<R> x = fetch_record<R>(rec_cell, rec, r);
+        store_record<R>(rec_cell2, rec2, beg + atomicAdd(&hist[raw_origin<R>(x, g.log2H)], 1u), x);
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// Work-group shapes, fixed per (precision, image size).  The FFTs run on a radix-8 base with
-// 8 elements per thread, so a 1024-thread work-group holds 8192 points in registers between
-// LDS exchanges and a CU keeps 16 waves (4 per SIMD) in flight at <= 128 VGPRs.
+// Work-group shapes, fixed per (precision, image size).  Each FFT runs on a base radix
+// 2^LR (2^LR elements per thread between LDS exchanges); the base radix of each pass and
+// the stacking block size are build-time choices (WSIMG_<precision>_LR1/_LR2/_PX2), picked
+// by measurement.
 //   pass 1: H grid rows per strip; the strip accumulates in float64 (16 B per cell) whatever
-//           the precision, so H * N <= 8192 cells; NT1 = H * N / 8 threads;
-//   pass 2: B image columns per block, B * N = 8192 (float) / 4096 (double) pixels,
-//           NT2 = B * N / 8 threads (8 output pixels each).
-constexpr int kLogRadix = 3;
-constexpr int kElems = 1 << kLogRadix;      // elements per thread in every FFT pass
+//           the precision, so H * N <= 8192 cells; NT1 = H * N / 2^LR1 threads;
+//   pass 2: B image columns per block, B * N = PX2 pixels, NT2 = B * N / 2^LR2 threads.
+#ifndef WSIMG_F32_LR1
+#define WSIMG_F32_LR1 4
+#endif
+#ifndef WSIMG_F32_LR2
+#define WSIMG_F32_LR2 4
+#endif
+#ifndef WSIMG_F64_LR1
+#define WSIMG_F64_LR1 4
+#endif
+#ifndef WSIMG_F64_LR2
+#define WSIMG_F64_LR2 3
+#endif
+// cells of one gridding strip (H * N): its float64 accumulator takes 16 B per cell of LDS
+#ifndef WSIMG_STRIP_CELLS
+#define WSIMG_STRIP_CELLS 8192
+#endif
+static_assert(WSIMG_STRIP_CELLS <= 8192, "origins of a strip index an 8192-bin histogram");
+#ifndef WSIMG_F32_PX2
+#define WSIMG_F32_PX2 4096
+#endif
+#ifndef WSIMG_F64_PX2
+#define WSIMG_F64_PX2 4096
+#endif
+// 1: the stacking pass re-reads its twiddles every plane instead of keeping them in
+// registers across planes (measured: keeping them is faster at every size timed)
+#ifndef WSIMG_COLS_TW_OPAQUE
+#define WSIMG_COLS_TW_OPAQUE 0
+#endif
 
 template <typename R, int LOG2N> struct Shape {
     static constexpr int N = 1 << LOG2N;
-    static constexpr int CAP1 = 8192;
-    static constexpr int H0 = CAP1 / N < 32 ? CAP1 / N : 32;
+    // base radices (log2), at most log2(N) - 1 so that a transform has two passes or more
+    static constexpr int LR1_0 = sizeof(R) == 4 ? WSIMG_F32_LR1 : WSIMG_F64_LR1;
+    static constexpr int LR2_0 = sizeof(R) == 4 ? WSIMG_F32_LR2 : WSIMG_F64_LR2;
+    static constexpr int LR1 = LR1_0 < LOG2N ? LR1_0 : LOG2N - 1;
+    static constexpr int LR2 = LR2_0 < LOG2N ? LR2_0 : LOG2N - 1;
+    static constexpr int E1 = 1 << LR1, E2 = 1 << LR2;
+    static constexpr int CAP1 = WSIMG_STRIP_CELLS;
+    static constexpr int H0 = CAP1 / N < 32 ? (CAP1 / N < 1 ? 1 : CAP1 / N) : 32;   // a row at least
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
-    static constexpr int NT1 = (H * N / kElems) < 64 ? 64 : (H * N / kElems);
-    static constexpr int PX2 = sizeof(R) == 4 ? 8192 : 4096;
+    static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);
+    static constexpr int PX2 = sizeof(R) == 4 ? WSIMG_F32_PX2 : WSIMG_F64_PX2;
     static constexpr int B0 = PX2 / N < N ? PX2 / N : N;
     static constexpr int B = B0 < 1 ? 1 : B0;
-    static constexpr int NT2 = (B * N / kElems) < 64 ? 64 : (B * N / kElems);
+    static constexpr int NT2 = (B * N / E2) < 64 ? 64 : (B * N / E2);
     static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
     static constexpr size_t LDS1_BYTES = (size_t)LDS1 * sizeof(double2);   // float64 accumulation
     static constexpr int LDS2 = lds_padded_elems_c(B * N);                 // complex elements
     // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer
     static constexpr bool NM1_LDS =
-        (size_t)LDS2 * 2 * sizeof(R) + sizeof(double) * kElems * NT2 <= 160 * 1024;
+        (size_t)LDS2 * 2 * sizeof(R) + sizeof(double) * E2 * NT2 <= 160 * 1024;
     static constexpr size_t LDS2_BYTES =
-        (size_t)LDS2 * 2 * sizeof(R) + (NM1_LDS ? sizeof(double) * kElems * NT2 : 0);
+        (size_t)LDS2 * 2 * sizeof(R) + (NM1_LDS ? sizeof(double) * E2 * NT2 : 0);
 };
 
 // ---------------------------------------------------------------------------------------
@@ -486,8 +628,28 @@ template <typename R, int LOG2N> struct Shape {
 // 2500 for W = 7), and float32 atomic accumulation alone costs ~1e-5 of the image there.
 // The per-tap products are formed in the plan's precision; the float path converts the
 // strip to float32 in place before its FFT.
-// One occupied strip (plane k, strip s) by the whole work-group.
-template <typename R, bool FFT, int LOG2N>
+//
+// Each lane walks a chunk of consecutive records (records are in (bucket, origin) order) for
+// RW grid rows of the strip at a time, summing the taps of a run of equal-origin records in
+// float64 registers (RW x WMAX complex values; each tap product is still formed in the plan
+// precision, so the sums match per-tap float64 accumulation up to order) and adding them to
+// the LDS strip when the origin changes or the chunk ends.  (Float32 run sums cost up to
+// 4e-6 of the image peak near the edges, where the taper amplifies grid rounding.)  The chunk length grows with the records the
+// strip reads (one record per lane up to NT records, at most kChunkMax), so sparse strips
+// keep every lane busy and dense ones merge long runs.
+#ifndef WSIMG_GRID_CHUNK_MAX
+#define WSIMG_GRID_CHUNK_MAX 32
+#endif
+constexpr uint32_t kChunkMax = WSIMG_GRID_CHUNK_MAX;
+
+// Register rows per walk for a support class WMAX: the accumulators stay within 64 VGPRs.
+template <typename R, int WMAX> struct WalkRows {
+    static constexpr int words = WMAX * 4;
+    static constexpr int value = 64 / words >= 4 ? 4 : (64 / words >= 2 ? 2 : 1);
+};
+
+// One occupied strip (plane k of channel c, strip s) by the whole work-group.
+template <typename R, bool FFT, int LOG2N, int WMAX>
 __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, unsigned char* smem_raw,
                                            const uint32_t* __restrict__ offsets,
                                            const uint32_t* __restrict__ rec_cell,
@@ -499,6 +661,8 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
     constexpr int n = SH::N, H = SH::H, NT = SH::NT1, nmask = n - 1;
     constexpr int LOG2H = Log2Of<H>::value_any;
     constexpr int elems = H * n;
+    constexpr int RW = WalkRows<R, WMAX>::value < H ? WalkRows<R, WMAX>::value : H;
+    constexpr int NG = H / RW, LOG2NG = Log2Of<NG>::value_any;
     double2* acc = reinterpret_cast<double2*>(smem_raw);
     C* lds = reinterpret_cast<C*>(smem_raw);
     const int tid = threadIdx.x;
@@ -510,37 +674,81 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
     int s_lo = (row0 - (W - 1)) >> LOG2H;
     if (s_lo < 0) s_lo = 0;
     constexpr int shift = FFT ? (n >> 1) : 0;   // place cell q at (q + n/2) mod n: the centring
-    for (int sp = s_lo; sp <= s; ++sp) {
-        const int bucket = c * g.nb1 + k * g.S + sp;
-        const uint32_t beg = offsets[(size_t)bucket << kLogReplicas];
-        const uint32_t end = offsets[(size_t)(bucket + 1) << kLogReplicas];
-        for (uint32_t r = beg + tid; r < end; r += NT) {
+    const int bucket0 = c * g.nb1 + k * g.S;
+    const uint32_t vbeg = offsets[(size_t)(bucket0 + s_lo) << kLogReplicas];
+    const uint32_t vend = offsets[(size_t)(bucket0 + s + 1) << kLogReplicas];
+    const uint32_t nv = vend - vbeg;
+    uint32_t chunk = nv / NT;
+    chunk = chunk < 1u ? 1u : (chunk > kChunkMax ? kChunkMax : chunk);
+    const uint32_t items = ((nv + chunk - 1) / chunk) << LOG2NG;
+
+    for (uint32_t it = tid; it < items; it += NT) {
+        const int rlo = row0 + (int)(it & (NG - 1)) * RW;     // first grid row of this walk
+        uint32_t r = vbeg + (it >> LOG2NG) * chunk;
+        const uint32_t re = r + chunk < vend ? r + chunk : vend;
+        int sp = s_lo;
+        uint32_t bend = offsets[(size_t)(bucket0 + sp + 1) << kLogReplicas];
+        double2 sum[RW][WMAX];
+#pragma unroll
+        for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+            for (int a = 0; a < WMAX; ++a) sum[rr][a] = make_double2(0.0, 0.0);
+        int cq = -1, cp = 0;
+        // add the run's sums to the strip (rows of the walk that origin (cq, cp) reaches)
+        auto flush = [&]() {
+            if (cq < 0) return;
+#pragma unroll
+            for (int rr = 0; rr < RW; ++rr) {
+                const int b = rlo + rr - cp;
+                if ((unsigned)b < (unsigned)W) {
+                    const int lrow = (rlo + rr - row0) << LOG2N;
+#pragma unroll
+                    for (int a = 0; a < WMAX; ++a) {
+                        if (a < W) {
+                            double2* dst = &acc[lds_pad(lrow + ((cq + a + shift) & nmask))];
+                            atomicAdd(&dst->x, sum[rr][a].x);
+                            atomicAdd(&dst->y, sum[rr][a].y);
+                        }
+                        sum[rr][a] = make_double2(0.0, 0.0);
+                    }
+                }
+            }
+        };
+        for (; r < re; ++r) {
+            while (r >= bend) {
+                ++sp;
+                bend = offsets[(size_t)(bucket0 + sp + 1) << kLogReplicas];
+            }
             int q0, p0;
             C fr, v;
-            load_record<R>(rec_cell, rec, r, sp, LOG2H, q0, p0, fr, v);
-            int b_lo = row0 - p0;
-            if (b_lo < 0) b_lo = 0;
-            int b_hi = row0 + H - 1 - p0;
-            if (b_hi > W - 1) b_hi = W - 1;
-            if (b_lo > b_hi) continue;
-            R gx[kMaxSupport];
+            decode_record<R>(fetch_record<R>(rec_cell, rec, r), sp, LOG2H, q0, p0, fr, v);
+            if (q0 != cq || p0 != cp) {
+                flush();
+                cq = q0;
+                cp = p0;
+            }
+            if (rlo + RW - 1 < p0 || rlo > p0 + W - 1) continue;     // no tap row in this walk
+            R gx[WMAX];
 #pragma unroll
-            for (int a = 0; a < kMaxSupport; ++a)
+            for (int a = 0; a < WMAX; ++a)
                 if (a < W) gx[a] = kb_tap<R>(kbc, a, fr.x);
-            for (int b = b_lo; b <= b_hi; ++b) {
-                const R gy = kb_tap<R>(kbc, b, fr.y);
-                const R vr = v.x * gy, vi = v.y * gy;
-                const int lrow = (p0 + b - row0) << LOG2N;
 #pragma unroll
-                for (int a = 0; a < kMaxSupport; ++a) {
-                    if (a < W) {
-                        double2* dst = &acc[lds_pad(lrow + ((q0 + a + shift) & nmask))];
-                        atomicAdd(&dst->x, (double)(vr * gx[a]));
-                        atomicAdd(&dst->y, (double)(vi * gx[a]));
+            for (int rr = 0; rr < RW; ++rr) {
+                const int b = rlo + rr - p0;
+                if ((unsigned)b < (unsigned)W) {
+                    const R gy = kb_tap<R>(kbc, b, fr.y);
+                    const R vr = v.x * gy, vi = v.y * gy;
+#pragma unroll
+                    for (int a = 0; a < WMAX; ++a) {
+                        if (a < W) {
+                            sum[rr][a].x += (double)(vr * gx[a]);
+                            sum[rr][a].y += (double)(vi * gx[a]);
+                        }
                     }
                 }
             }
         }
+        flush();
     }
     __syncthreads();
 
@@ -568,7 +776,7 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                 __syncthreads();
             }
         }
-        fft_rows_lds<LOG2N, kLogRadix, H, NT>(lds, tw);
+        fft_rows_lds<LOG2N, SH::LR1, H, NT>(lds, tw);
         // column-block layout [k][jb][p'][B], p' = (p + n/2) mod n: the next pass reads a
         // contiguous [n][B] block per plane.  Image column j takes FFT bin (j + n/2) mod n.
         constexpr int B = SH::B, LOG2B = Log2Of<B>::value_any;
@@ -593,7 +801,7 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
 
 // The gridding step alone: work-group (b, c) = strip b of every plane of channel c; empty
 // strips are zeroed.
-template <typename R, int LOG2N>
+template <typename R, int LOG2N, int WMAX>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
 k_grid_only(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restrict__ occ,
             const uint32_t* __restrict__ rec_cell, const void* __restrict__ rec, const R* __restrict__ kbc,
@@ -608,13 +816,13 @@ k_grid_only(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
         for (int e = threadIdx.x; e < SH::H * SH::N; e += SH::NT1) dst[e] = cmake<C>((R)0, (R)0);
         return;
     }
-    grid_strip<R, false, LOG2N>(g, c, k, s, smem_raw, offsets, rec_cell, rec, kbc, nullptr, out);
+    grid_strip<R, false, LOG2N, WMAX>(g, c, k, s, smem_raw, offsets, rec_cell, rec, kbc, nullptr, out);
 }
 
 // Gridding + row FFT: a persistent grid walks the work list of occupied strips of all
 // channels (heavy ones first) through an atomic counter; every work-group leaves once the
 // list is exhausted.
-template <typename R, int LOG2N>
+template <typename R, int LOG2N, int WMAX>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
 k_grid_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
             const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
@@ -638,7 +846,7 @@ k_grid_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restri
         if (b < 0) break;
         const int c = b / g.nb1, bb = b - c * g.nb1;
         const int k = bb / g.S, s = bb - k * g.S;
-        grid_strip<R, true, LOG2N>(g, c, k, s, smem_raw, offsets, rec_cell, rec, kbc, opaque_ptr(tw), out);
+        grid_strip<R, true, LOG2N, WMAX>(g, c, k, s, smem_raw, offsets, rec_cell, rec, kbc, opaque_ptr(tw), out);
         __syncthreads();
     }
 }
@@ -646,9 +854,9 @@ k_grid_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restri
 // ---------------------------------------------------------------------------------------
 // column FFTs, w-phase, stacking over planes, taper
 //
-// Work-group = one block of B image columns, 8 pixels per thread.  Per plane:
-//   * the inputs of the first radix-8 pass come straight from HBM into registers (thread
-//     tid = b * B + c takes column c at rows b + m N/8, so a wave reads 64 consecutive
+// Work-group = one block of B image columns, E = 2^LR2 pixels per thread.  Per plane:
+//   * the inputs of the first radix-E pass come straight from HBM into registers (thread
+//     tid = b * B + c takes column c at rows b + m N/E, so a wave reads 64 consecutive
 //     elements of the contiguous [n][B] block); rows of empty strips read as 0;
 //   * the middle passes run in LDS, the last pass leaves its outputs in registers;
 //   * each output is multiplied by exp(+2 pi i w_k (n - 1)) and its real part summed over
@@ -658,15 +866,15 @@ k_grid_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restri
 
 template <typename R> struct Pass2Prefetch { static constexpr bool value = sizeof(R) == 4; };
 
-template <typename R, int LOG2N, int B>
+template <typename R, int LOG2N, int LR, int B>
 __device__ __forceinline__ void pass2_load(const typename Cx<R>::T* __restrict__ src,
                                            const uint8_t* __restrict__ occk, int tid, bool active,
                                            int log2H, typename Cx<R>::T* x) {
     using C = typename Cx<R>::T;
-    constexpr int n = 1 << LOG2N, hn = n >> 1, nr = n >> kLogRadix;
+    constexpr int n = 1 << LOG2N, hn = n >> 1, nr = n >> LR;
     const int b = tid / B;
 #pragma unroll
-    for (int m = 0; m < kElems; ++m) {
+    for (int m = 0; m < (1 << LR); ++m) {
         x[m] = cmake<C>((R)0, (R)0);
         const int pp = b + m * nr;
         const int p = (pp + hn) & (n - 1);
@@ -685,8 +893,8 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     constexpr int n = SH::N, nmask = n - 1, hn = n >> 1;
     constexpr int B = SH::B, NT = SH::NT2, LOG2B = Log2Of<B>::value_any;
     constexpr int elems = B * n;
-    constexpr int E = kElems;
-    static_assert(LOG2N > kLogRadix, "image side must exceed the base radix");
+    constexpr int LR = SH::LR2, E = SH::E2;
+    static_assert(LOG2N > LR, "image side must exceed the base radix");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* lds = reinterpret_cast<C*>(smem_raw);
     // n - 1 of each output slot: in LDS after the FFT buffer (nm1s[s * NT + tid]) when it
@@ -696,7 +904,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     nm1r[0] = 0.0;
     const int jb = blockIdx.x, c = blockIdx.y;
     const int tid = threadIdx.x;
-    const bool first_active = tid < (elems >> kLogRadix);
+    const bool first_active = tid < (elems >> LR);
     const uint8_t* pocc = plane_occ + (size_t)c * g.nw;
     const uint8_t* socc = occ + (size_t)c * g.nb1;
     const typename Cx<R>::T* cin = inter + ((size_t)c * g.nw << (2 * LOG2N));
@@ -710,7 +918,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         if constexpr (sizeof(R) == 4) comp[s] = (R)0;
         int col, ip;
         double v = 0.0;
-        if (last_slot<LOG2N, kLogRadix, B, NT>(tid, s, col, ip)) {
+        if (last_slot<LOG2N, LR, B, NT>(tid, s, col, ip)) {
             const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
             const double l = (double)(j - hn) * g.pixel, m = (double)(i - hn) * g.pixel;
             const double r2 = m * m + l * l;
@@ -725,7 +933,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     while (k < g.nw && !pocc[k]) ++k;
     C x[E], pf[E];
     if (k < g.nw)
-        pass2_load<R, LOG2N, B>(cin + ((size_t)k << (2 * LOG2N)) + (size_t)jb * elems,
+        pass2_load<R, LOG2N, LR, B>(cin + ((size_t)k << (2 * LOG2N)) + (size_t)jb * elems,
                                 socc + (size_t)k * g.S, tid, first_active, g.log2H, pf);
     while (k < g.nw) {
         int kn = k + 1;
@@ -734,21 +942,21 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         for (int m = 0; m < E; ++m) x[m] = pf[m];
         if constexpr (Pass2Prefetch<R>::value) {
             if (kn < g.nw)
-                pass2_load<R, LOG2N, B>(cin + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
+                pass2_load<R, LOG2N, LR, B>(cin + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
                                         socc + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
         }
-        // first pass: radix 8 with L = 1 (no twiddles), registers to LDS
+        // first pass: radix E with L = 1 (no twiddles), registers to LDS
         if (first_active) {
-            dft8(x);
+            dft_small<E>(x);
             const int col = tid % B, b = tid / B;
-            const int base = (col << LOG2N) + (b << kLogRadix);
+            const int base = (col << LOG2N) + (b << LR);
 #pragma unroll
             for (int m = 0; m < E; ++m) lds[lds_pad(base + m)] = x[m];
         }
         __syncthreads();
-        const C* twk = opaque_ptr(tw);
-        stockham_range<LOG2N, kLogRadix, kLogRadix, FftPlan<LOG2N, kLogRadix>::LAST_L, B, NT>(lds, twk);
-        fft_last_to_regs<LOG2N, kLogRadix, B, NT>(lds, twk, x);
+        const C* twk = WSIMG_COLS_TW_OPAQUE ? opaque_ptr(tw) : tw;
+        stockham_range<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L, B, NT>(lds, twk);
+        fft_last_to_regs<LOG2N, LR, B, NT>(lds, twk, x);
         double wk;
         {
 #pragma clang fp contract(off)
@@ -779,7 +987,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         }
         if constexpr (!Pass2Prefetch<R>::value) {
             if (kn < g.nw)
-                pass2_load<R, LOG2N, B>(cin + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
+                pass2_load<R, LOG2N, LR, B>(cin + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
                                         socc + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
         }
         __syncthreads();
@@ -790,7 +998,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         int col, ip;
-        if (last_slot<LOG2N, kLogRadix, B, NT>(tid, s, col, ip)) {
+        if (last_slot<LOG2N, LR, B, NT>(tid, s, col, ip)) {
             const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
             image[((size_t)c << (2 * LOG2N)) + (size_t)i * n + j] =
                 sum_w > 0.0 ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;

@@ -35,7 +35,7 @@ wsimg_status fail(wsimg_status s, const std::string& msg) {
     } while (0)
 
 const char* kStageNames[WSIMG_N_KERNELS] = {"zero_counts", "reduce", "key", "scan",
-                                            "scatter", "grid_rows", "cols_stack"};
+                                            "scatter", "origin_sort", "grid_rows", "cols_stack"};
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
@@ -67,8 +67,8 @@ struct wsimg_plan {
     uint8_t *occ = nullptr, *plane_occ = nullptr;
     uint32_t* list = nullptr;      // work list of occupied strips
     int persist_blocks = 256;      // work-groups of the persistent gridding kernel
-    uint32_t *key = nullptr, *rank = nullptr, *rec_cell = nullptr;
-    void *rec = nullptr, *inter = nullptr;
+    uint32_t *key = nullptr, *rank = nullptr, *rec_cell = nullptr, *rec_cell2 = nullptr;
+    void *rec = nullptr, *rec2 = nullptr, *inter = nullptr;   // records by bucket; by (bucket, origin)
     void *tw = nullptr, *inv_taper = nullptr, *kbc = nullptr;
     int64_t device_bytes = 0;
     std::vector<void*> allocations;
@@ -178,9 +178,13 @@ wsimg_status configure_shape(wsimg_plan* pl) {
     pl->nt2 = SH::NT2;
     pl->lds1 = SH::LDS1_BYTES;
     pl->lds2 = SH::LDS2_BYTES;
-    WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N>,
+    WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, 7>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
-    WS_HIP(hipFuncSetAttribute((const void*)k_grid_only<R, LOG2N>,
+    WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, kMaxSupport>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
+    WS_HIP(hipFuncSetAttribute((const void*)k_grid_only<R, LOG2N, 7>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
+    WS_HIP(hipFuncSetAttribute((const void*)k_grid_only<R, LOG2N, kMaxSupport>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
@@ -193,21 +197,28 @@ wsimg_status configure_shape(wsimg_plan* pl) {
         if (e_ != hipSuccess) return fail(WSIMG_E_HIP, std::string("launch ") + what + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-template <typename R, int LOG2N>
-wsimg_status launch_grid_rows(wsimg_plan* pl, int nch, bool fft, void* out) {
+// WMAX: the support class the gridding registers are sized for (W <= 7, else W <= 15).
+template <typename R, int LOG2N, int WMAX>
+wsimg_status launch_grid_w(wsimg_plan* pl, int nch, bool fft, void* out) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
     if (fft) {
-        hipLaunchKernelGGL((k_grid_rows<R, LOG2N>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1), pl->lds1,
-                           pl->stream, g, nch, pl->worklist, pl->list, pl->offsets, pl->rec_cell,
-                           (const void*)pl->rec, (const R*)pl->kbc, (const C*)pl->tw, (C*)out);
+        hipLaunchKernelGGL((k_grid_rows<R, LOG2N, WMAX>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1),
+                           pl->lds1, pl->stream, g, nch, pl->worklist, pl->list, pl->offsets, pl->rec_cell2,
+                           (const void*)pl->rec2, (const R*)pl->kbc, (const C*)pl->tw, (C*)out);
     } else {
-        hipLaunchKernelGGL((k_grid_only<R, LOG2N>), dim3((unsigned)(g.nw * g.S), (unsigned)nch), dim3(pl->nt1),
-                           pl->lds1, pl->stream, g, pl->offsets, pl->occ, pl->rec_cell, (const void*)pl->rec,
-                           (const R*)pl->kbc, (C*)out);
+        hipLaunchKernelGGL((k_grid_only<R, LOG2N, WMAX>), dim3((unsigned)(g.nw * g.S), (unsigned)nch),
+                           dim3(pl->nt1), pl->lds1, pl->stream, g, pl->offsets, pl->occ, pl->rec_cell2,
+                           (const void*)pl->rec2, (const R*)pl->kbc, (C*)out);
     }
     WS_LAUNCH_CHECK("grid_rows");
     return WSIMG_OK;
+}
+
+template <typename R, int LOG2N>
+wsimg_status launch_grid_rows(wsimg_plan* pl, int nch, bool fft, void* out) {
+    return pl->g.support <= 7 ? launch_grid_w<R, LOG2N, 7>(pl, nch, fft, out)
+                              : launch_grid_w<R, LOG2N, kMaxSupport>(pl, nch, fft, out);
 }
 
 template <typename R, int LOG2N>
@@ -376,6 +387,13 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
         WS_LAUNCH_CHECK("scatter");
     }
     if (auto r = st.after(4)) return r;
+
+    if (M > 0) {
+        hipLaunchKernelGGL((k_origin_sort<R>), dim3((unsigned)pl->nb, nch), dim3(kSortThreads), 0, s, g,
+                           pl->offsets, pl->rec_cell, (const void*)pl->rec, pl->rec_cell2, pl->rec2);
+        WS_LAUNCH_CHECK("origin_sort");
+    }
+    if (auto r = st.after(5)) return r;
     return WSIMG_OK;
 }
 
@@ -387,14 +405,14 @@ wsimg_status run_image(wsimg_plan* pl, const Batch& bt, const double* uvw, const
     if (auto r = run_sort<R>(pl, st, bt, uvw, vis, wts)) return r;
     if (grid_only) {
         if (auto r = grid_rows<R>(pl, bt.nch, false, image)) return r;
-        if (auto r = st.after(5)) return r;
         if (auto r = st.after(6)) return r;
+        if (auto r = st.after(7)) return r;
         return WSIMG_OK;
     }
     if (auto r = grid_rows<R>(pl, bt.nch, true, pl->inter)) return r;
-    if (auto r = st.after(5)) return r;
-    if (auto r = cols_stack<R>(pl, bt.nch, image)) return r;
     if (auto r = st.after(6)) return r;
+    if (auto r = cols_stack<R>(pl, bt.nch, image)) return r;
+    if (auto r = st.after(7)) return r;
     return WSIMG_OK;
 }
 
@@ -503,6 +521,8 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
     ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * mv, "record cells");
     ALLOC(rec, (f32 ? 16 : 32) * mv, "records");
+    ALLOC(rec_cell2, f32 ? 256 : sizeof(uint32_t) * mv, "record cells by origin");
+    ALLOC(rec2, (f32 ? 16 : 32) * mv, "records by origin");
     ALLOC(inter, pl->cbytes * cells * mc, "row-transformed planes");
     ALLOC(tw, pl->cbytes * n, "twiddles");
     ALLOC(inv_taper, pl->rbytes * n, "taper");
