@@ -35,6 +35,8 @@ def lib():
         L.oracle_grid_accumulate.restype = None
         L.oracle_dft.argtypes = [i64, p, p, p, p, p, i64, p, p, p, p]
         L.oracle_dft.restype = None
+        L.oracle_degrid.argtypes = [i64, i64, i64, p, p, p, p, p, p]
+        L.oracle_degrid.restype = None
         _lib = L
     return _lib
 

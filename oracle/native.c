@@ -6,6 +6,8 @@
  *   separable kernel, one visibility at a time, into one complex float64 plane.
  * oracle_dft: the direct sum over visibilities that inverts Eq. 1 (with the
  *   w-term), evaluated at a list of pixels.
+ * oracle_degrid: the transpose of oracle_grid_accumulate: each visibility reads
+ *   the W x W cells its taps cover, weighted by the same separable kernel.
  */
 #include <math.h>
 #include <stdint.h>
@@ -54,5 +56,26 @@ void oracle_dft(int64_t nvis, const double *u, const double *v, const double *w,
         }
         out[2 * p] = sr;
         out[2 * p + 1] = si;
+    }
+}
+
+/* out[c] = sum_{a,b} gx[c][a] * gy[c][b] * grid[p0[c]+b][q0[c]+a] for each of count rows. */
+void oracle_degrid(int64_t n, int64_t support, int64_t count, const int64_t *p0, const int64_t *q0,
+                   const double *gx, const double *gy, const double *grid /* [n][n][2] */,
+                   double *out /* [count][2] */)
+{
+    for (int64_t c = 0; c < count; ++c) {
+        double sr = 0.0, si = 0.0;
+        for (int64_t b = 0; b < support; ++b) {
+            double gyb = gy[c * support + b];
+            for (int64_t a = 0; a < support; ++a) {
+                double g = gx[c * support + a] * gyb;
+                int64_t cell = (p0[c] + b) * n + (q0[c] + a);
+                sr += grid[2 * cell] * g;
+                si += grid[2 * cell + 1] * g;
+            }
+        }
+        out[2 * c] = sr;
+        out[2 * c + 1] = si;
     }
 }

@@ -189,11 +189,12 @@ def direction_cosines(n: int, pixel_rad: float, rows, cols):
 def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
                  pixels: Optional[Tuple[Sequence[int], Sequence[int]]] = None,
                  planes: Optional[Sequence[int]] = None, complex_out: bool = False,
-                 prepared: Optional[Prepared] = None) -> np.ndarray:
+                 prepared: Optional[Prepared] = None, normalize: bool = True) -> np.ndarray:
     """Steps 1-8: the dirty image [N, N] (or [|I|, |J|] at pixels = (I, J)).
 
     ``planes`` restricts steps 5-7 to a subset of w-planes (the rest contribute
-    nothing); the normalisation keeps the full sum of weights.
+    nothing); the normalisation keeps the full sum of weights.  normalize=False leaves
+    out the division by the sum of weights (the imaging operator itself).
     """
     n = prm.n
     pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
@@ -202,7 +203,7 @@ def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
     else:
         rows, cols = np.asarray(pixels[0]), np.asarray(pixels[1])
     shape = (rows.size, cols.size)
-    if pr.sum_w == 0.0:
+    if pr.sum_w == 0.0 and normalize:
         return np.zeros(shape, dtype=np.complex128 if complex_out else np.float64)
     _, _, nm1 = direction_cosines(n, prm.pixel_rad, rows, cols)
     S = np.zeros(shape, dtype=np.complex128)
@@ -225,7 +226,7 @@ def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
     xi_j = (cols - n // 2) / n
     xi_i = (rows - n // 2) / n
     corr = np.outer(_kb.kb_taper(xi_i, prm.support, prm.beta), _kb.kb_taper(xi_j, prm.support, prm.beta))
-    D = S / (pr.sum_w * corr)
+    D = S / ((pr.sum_w if normalize else 1.0) * corr)
     return D if complex_out else D.real
 
 
@@ -234,3 +235,48 @@ def grid_stack(uvw_m, vis, weights, freq_hz: float, prm: Params,
     """Step 5 for every plane: the complex float64 grid [Nw, N, N]."""
     pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
     return np.stack([grid_plane(pr, vis, weights, prm, k) for k in range(prm.n_wplanes)])
+
+
+def wstack_predict(uvw_m, weights, freq_hz: float, prm: Params, image: np.ndarray,
+                   prepared: Optional[Prepared] = None) -> np.ndarray:
+    """Prediction (degridding): the transpose of the unnormalised imaging operator.
+
+    With A the map z -> Re S(z) / (C(xi_i) C(xi_j)) of steps 5-8 (gridding z_m = W_m V_m,
+    normalize=False), this returns y = A^T X, so that for every complex z and real X
+        sum_ij A(z)_ij X_ij = Re sum_m z_m conj(y_m).
+    The steps of Sec. 2 run backwards:
+      8'. divide the image by the kernel's transform on both axes:  Y = X / (C(xi_i) C(xi_j));
+      7'. per plane, the conjugate w-phase:  Y_k = Y exp(-2 pi i w_k (n_ij - 1));
+      6'. the transform with the - sign, phase centre at N/2:
+          g_k[p][q] = sum_{i,j} Y_k(i,j) exp(-2 pi i [(q-N/2)(j-N/2) + (p-N/2)(i-N/2)] / N)
+                    = fftshift(fft2(ifftshift(Y_k)))   (numpy's fft has the - sign);
+      5'. each kept row reads its taps:  y_m = sum_{a,b} G(q0+a-x_m) G(p0+b-y_m) g_k[p0+b][q0+a].
+    Dropped rows predict 0.  ``weights`` only decide which rows are kept and the plane range
+    (as in steps 2-3); they do not scale the prediction.
+    """
+    n = prm.n
+    pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
+    rows = cols = np.arange(n)
+    _, _, nm1 = direction_cosines(n, prm.pixel_rad, rows, cols)
+    xi = (rows - n // 2) / n
+    ck = _kb.kb_taper(xi, prm.support, prm.beta)
+    Y = np.asarray(image, dtype=np.float64) / np.outer(ck, ck)
+    out = np.zeros(pr.u.shape[0], dtype=np.complex128)
+    L = _lib()
+    for k in range(prm.n_wplanes):
+        sel = np.nonzero(pr.keep & (pr.k == k))[0]
+        if sel.size == 0:
+            continue
+        wk = pr.w_lo + (k + 0.5) * pr.dw
+        cyc = wk * nm1
+        cyc = cyc - np.round(cyc)
+        g = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(Y * np.exp(-2j * math.pi * cyc))))
+        gri = np.ascontiguousarray(np.stack([g.real, g.imag], axis=-1))
+        gx, gy = tap_weights(pr, prm, sel)
+        p0 = np.ascontiguousarray(pr.p0[sel])
+        q0 = np.ascontiguousarray(pr.q0[sel])
+        res = np.zeros((sel.size, 2), dtype=np.float64)
+        L.oracle_degrid(n, prm.support, sel.size, _ptr(p0), _ptr(q0), _ptr(gx), _ptr(gy), _ptr(gri),
+                        _ptr(res))
+        out[sel] = res[:, 0] + 1j * res[:, 1]
+    return out
