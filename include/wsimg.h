@@ -55,6 +55,9 @@ typedef enum {
 
 /* wsimg_params.flags */
 #define WSIMG_FIXED_WRANGE 0x1u   /* use w_lo/w_hi below instead of the data's range     */
+#define WSIMG_UNNORMALIZED 0x2u   /* wsimg_image does not divide by the sum of weights:
+                                     the image is then A(W V), the imaging operator that
+                                     wsimg_predict is the transpose of                    */
 
 typedef struct {
     int32_t n;          /* image side = grid side: a power of two, 16..8192 (16384 is
@@ -181,6 +184,28 @@ wsimg_status wsimg_image(wsimg_plan *plan, int64_t n_vis, const double *uvw_m,
 wsimg_status wsimg_image_batch(wsimg_plan *plan, int32_t n_channels, const int64_t *row_counts,
                                const double *uvw_m, const void *vis, const void *weights,
                                const double *freqs_hz, void *images_out, wsimg_stats *stats);
+
+/*
+ * Prediction (degridding): the transpose of the imaging operator, image -> visibilities.
+ * With A the unnormalised imaging map of wsimg_image (WSIMG_UNNORMALIZED, gridding z_m =
+ * W_m V_m), this computes y = A^T X for a real image X:
+ *   Y_k = X / (C(xi_i) C(xi_j)) * exp(-2 pi i w_k (n_ij - 1)),
+ *   g_k[p][q] = sum_{i,j} Y_k(i,j) exp(-2 pi i [(q-N/2)(j-N/2) + (p-N/2)(i-N/2)] / N),
+ *   y_m = sum_{a,b} G(q0+a-x_m) G(p0+b-y_m) g_{k_m}[p0+b][q0+a],
+ * so that sum_ij A(z)_ij X_ij = Re sum_m z_m conj(y_m) for every z.  It is the forward model
+ * (Eq. 1 with the w-stacking approximation) that a data-fidelity loss differentiates through.
+ *  uvw_m, freq_hz : as wsimg_image.
+ *  weights   : device, [n_vis]; they only decide which rows are kept (finite) and the plane
+ *              range (rows with positive weight), exactly as in wsimg_image; they do not
+ *              scale the prediction.  Use WSIMG_FIXED_WRANGE to pin the planes.
+ *  image_in  : device, [n][n] float (F32) / double (F64), row-major.
+ *  vis_out   : device, [n_vis] interleaved complex of the plan's precision; fully
+ *              overwritten (dropped rows get 0).
+ *  stats     : as wsimg_image (no WSIMG_E_EMPTY: a prediction needs no weights).
+ * Errors: WSIMG_E_INVALID, WSIMG_E_CAPACITY, WSIMG_E_HIP.
+ */
+wsimg_status wsimg_predict(wsimg_plan *plan, int64_t n_vis, const double *uvw_m, const void *weights,
+                           double freq_hz, const void *image_in, void *vis_out, wsimg_stats *stats);
 
 /*
  * The gridding step alone (Eq. 3 with the separable kernel, nearest w-plane):

@@ -14,7 +14,7 @@ from typing import Optional, Tuple
 
 from . import _lib
 
-__all__ = ["WsimgError", "Plan", "image", "grid", "stage_names", "version"]
+__all__ = ["WsimgError", "Plan", "image", "grid", "predict", "stage_names", "version", "ImagingOperator"]
 
 
 class WsimgError(RuntimeError):
@@ -52,7 +52,8 @@ class Plan:
 
     def __init__(self, n: int, pixel_rad: float, n_wplanes: int, support: int = 7,
                  beta: Optional[float] = None, precision: str = "f32", max_vis: int = 0,
-                 w_range: Optional[Tuple[float, float]] = None, device=None, max_channels: int = 1):
+                 w_range: Optional[Tuple[float, float]] = None, device=None, max_channels: int = 1,
+                 normalize: bool = True):
         import torch
 
         self._torch = torch
@@ -69,6 +70,8 @@ class Plan:
         if w_range is not None:
             p.w_lo, p.w_hi = float(w_range[0]), float(w_range[1])
             p.flags |= _lib.WSIMG_FIXED_WRANGE
+        if not normalize:
+            p.flags |= _lib.WSIMG_UNNORMALIZED
         self._L = _lib.load()
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -156,6 +159,37 @@ class Plan:
             return out, [{f: getattr(st[c], f) for f, _ in _lib.Stats._fields_} for c in range(nch)]
         return out
 
+    def predict(self, uvw, weights, freq_hz: float, image, out=None, stats: bool = False):
+        """Prediction (wsimg_predict): visibilities [M] of the plan's complex dtype from a real
+        image [n, n]; the transpose of the unnormalised imaging operator."""
+        t = self._torch
+        cdt, rdt = self._dtypes()
+        m = int(uvw.shape[0]) if uvw.dim() == 2 else -1
+        if uvw.dtype != t.float64 or uvw.dim() != 2 or uvw.shape[1] != 3:
+            raise ValueError("uvw must be a float64 tensor of shape [M, 3] (metres)")
+        if weights.dtype != rdt or weights.shape != (m,):
+            raise ValueError(f"weights must be {rdt} of shape [M]")
+        if image.dtype != rdt or tuple(image.shape) != (self.n, self.n):
+            raise ValueError(f"image must be {rdt} of shape [n, n]")
+        for name, x in (("uvw", uvw), ("weights", weights), ("image", image)):
+            if x.device != self.device:
+                raise ValueError(f"{name} must live on {self.device}")
+            if not x.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+        if out is None:
+            out = t.empty((m,), dtype=cdt, device=self.device)
+        elif out.dtype != cdt or tuple(out.shape) != (m,) or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous [M] tensor of the plan's complex dtype on its device")
+        self._stream()
+        st = _lib.Stats()
+        _check(self._L.wsimg_predict(self._h, m, ctypes.c_void_p(uvw.data_ptr()),
+                                     ctypes.c_void_p(weights.data_ptr()), float(freq_hz),
+                                     ctypes.c_void_p(image.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.byref(st) if stats else None))
+        if stats:
+            return out, {f: getattr(st, f) for f, _ in _lib.Stats._fields_}
+        return out
+
     def grid(self, uvw, vis, weights, freq_hz: float, out=None, stats: bool = False):
         """The gridding step alone: complex grid [n_wplanes, n, n] (wsimg_grid)."""
         cdt, _ = self._dtypes()
@@ -220,3 +254,16 @@ def grid(uvw, vis, weights, freq_hz: float, *, n: int, pixel_rad: float, n_wplan
     with Plan(n, pixel_rad, n_wplanes, support, beta, precision, max_vis=uvw.shape[0],
               w_range=w_range, device=uvw.device) as p:
         return p.grid(uvw, vis, weights, freq_hz, stats=stats)
+
+
+def predict(uvw, weights, freq_hz: float, image, *, pixel_rad: float, n_wplanes: int, support: int = 7,
+            beta: Optional[float] = None, w_range=None, stats: bool = False):
+    """One-shot prediction (creates and frees a plan); precision from the image dtype."""
+    import torch
+    precision = "f64" if image.dtype == torch.float64 else "f32"
+    with Plan(int(image.shape[0]), pixel_rad, n_wplanes, support, beta, precision, max_vis=uvw.shape[0],
+              w_range=w_range, device=uvw.device) as p:
+        return p.predict(uvw, weights, freq_hz, image, stats=stats)
+
+
+from .operator import ImagingOperator  # noqa: E402

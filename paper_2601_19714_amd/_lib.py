@@ -18,12 +18,13 @@ WSIMG_E_UNSUPPORTED = -6
 WSIMG_F32 = 1
 WSIMG_F64 = 2
 WSIMG_FIXED_WRANGE = 0x1
+WSIMG_UNNORMALIZED = 0x2
 WSIMG_N_KERNELS = 8
 
 # every symbol include/wsimg.h declares
 EXPORTS = (
     "wsimg_plan_create", "wsimg_plan_create_batch", "wsimg_plan_destroy", "wsimg_plan_set_stream",
-    "wsimg_plan_get_info", "wsimg_image", "wsimg_image_batch", "wsimg_grid", "wsimg_set_timing", "wsimg_read_timing", "wsimg_stage_name",
+    "wsimg_plan_get_info", "wsimg_image", "wsimg_image_batch", "wsimg_predict", "wsimg_grid", "wsimg_set_timing", "wsimg_read_timing", "wsimg_stage_name",
     "wsimg_status_string", "wsimg_last_error", "wsimg_version",
 )
 
@@ -77,10 +78,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         f.argtypes = [vp, i64, vp, vp, vp, dbl, vp, ctypes.POINTER(Stats)]
     L.wsimg_image_batch.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, ctypes.POINTER(dbl), vp,
                                     ctypes.POINTER(Stats)]
+    L.wsimg_predict.argtypes = [vp, i64, vp, vp, dbl, vp, vp, ctypes.POINTER(Stats)]
     L.wsimg_set_timing.argtypes = [vp, i32]
     L.wsimg_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     for f in (L.wsimg_plan_create, L.wsimg_plan_create_batch, L.wsimg_plan_destroy, L.wsimg_plan_set_stream,
-              L.wsimg_plan_get_info, L.wsimg_image, L.wsimg_image_batch, L.wsimg_grid, L.wsimg_set_timing,
+              L.wsimg_plan_get_info, L.wsimg_image, L.wsimg_image_batch, L.wsimg_predict, L.wsimg_grid,
+              L.wsimg_set_timing,
               L.wsimg_read_timing):
         f.restype = ctypes.c_int
     L.wsimg_stage_name.argtypes = [i32]

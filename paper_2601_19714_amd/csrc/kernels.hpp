@@ -37,6 +37,7 @@ struct Geom {
     int nb1;                // buckets per channel: nw * S
     int B, log2B, NB;       // image columns per stacking block, blocks
     int fixed_range;
+    int unnormalized;       // the image is not divided by the sum of weights
     double du, half_n, pixel;
     double w_lo_fixed, w_hi_fixed;
 };
@@ -403,12 +404,14 @@ __device__ __forceinline__ uint32_t frac_code(double f) {
     return (uint32_t)(c < 0 ? 0 : (c > 8388607 ? 8388607 : c));
 }
 
+// vis may be null (prediction: the records carry positions only, W*V = 0); rec_idx, when not
+// null, receives each record's input row.
 template <typename R, typename WT>
 __global__ void __launch_bounds__(256)
 k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __restrict__ vis,
           const WT* __restrict__ wts, Geom g, const uint32_t* __restrict__ key,
           const uint32_t* __restrict__ rank, const uint32_t* __restrict__ offsets,
-          uint32_t* __restrict__ rec_cell, void* __restrict__ rec) {
+          uint32_t* __restrict__ rec_cell, void* __restrict__ rec, uint32_t* __restrict__ rec_idx) {
     using C = typename Cx<R>::T;
     const int c = blockIdx.y;
     const int64_t r0 = ch.row_off[c], r1 = ch.row_off[c + 1];
@@ -421,8 +424,9 @@ k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __re
     const uint32_t rep = blockIdx.x & (kReplicas - 1);     // the row block's replica (as in k_key)
     const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + rep] + rank[m];
     const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
-    const C v = vis[m];
+    const C v = vis ? vis[m] : cmake<C>((R)0, (R)0);
     const R w = (R)wts[m];
+    if (rec_idx) rec_idx[pos] = (uint32_t)m;
     if constexpr (sizeof(R) == 4) {
         const uint32_t ux = frac_code(rg.x - rg.cx), uy = frac_code(rg.y - rg.cy);
         const uint32_t pr = (uint32_t)p0 & (uint32_t)(g.H - 1);
@@ -994,15 +998,224 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         k = kn;
     }
 
-    const R inv_sw = sum_w > 0.0 ? (R)(1.0 / sum_w) : (R)0;
+    const bool scale_ok = g.unnormalized || sum_w > 0.0;
+    const R inv_sw = g.unnormalized ? (R)1 : (sum_w > 0.0 ? (R)(1.0 / sum_w) : (R)0);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         int col, ip;
         if (last_slot<LOG2N, LR, B, NT>(tid, s, col, ip)) {
             const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
             image[((size_t)c << (2 * LOG2N)) + (size_t)i * n + j] =
-                sum_w > 0.0 ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
+                scale_ok ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Prediction (degridding): the transpose of the unnormalised imaging operator.
+//
+// For a real image X, y_m = sum_{a,b} G(q0+a-x_m) G(p0+b-y_m) g_k[p0+b][q0+a] with
+//   g_k = the 2D transform with the - sign (phase centre N/2) of
+//         X / (C(xi_i) C(xi_j)) * exp(-2 pi i w_k (n_ij - 1)),
+// so that sum_ij A(z)_ij X_ij = Re sum_m z_m conj(y_m) for the imaging operator A of the
+// kernels above.  The - transform is taken as the conjugate of the + transform of the
+// conjugate, so the same FFT code and twiddles serve both directions.  The steps run in the
+// reverse order of imaging: columns first (k_adj_cols), then rows and the degridding
+// (k_adj_rows), over the same sort and the same occupied strips.
+
+// Work-group (jb, c) = block of B image columns of channel c.  Per occupied plane: the
+// conjugate of Y_k goes to LDS in bin order (image row i at position (i + N/2) mod N), one +
+// transform per column, and the conjugate of the result is written for the rows of occupied
+// strips in the intermediate's column-block layout (row p at p' = (p + N/2) mod N).
+template <typename R, int LOG2N>
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT2))
+k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ occ,
+           const uint8_t* __restrict__ plane_occ, const R* __restrict__ image,
+           const typename Cx<R>::T* __restrict__ tw, const R* __restrict__ inv_taper,
+           typename Cx<R>::T* __restrict__ inter) {
+    using C = typename Cx<R>::T;
+    using SH = Shape<R, LOG2N>;
+    constexpr int n = SH::N, nmask = n - 1, hn = n >> 1;
+    constexpr int B = SH::B, NT = SH::NT2, LOG2B = Log2Of<B>::value_any, LR = SH::LR2;
+    constexpr int elems = B * n;
+    constexpr int PER = (elems + NT - 1) / NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    const int jb = blockIdx.x, c = blockIdx.y;
+    const int tid = threadIdx.x;
+    const uint8_t* pocc = plane_occ + (size_t)c * g.nw;
+    const uint8_t* socc = occ + (size_t)c * g.nb1;
+    const R* img = image + ((size_t)c << (2 * LOG2N));
+
+    // this thread's pixels e = tid + t * NT (column (e >> LOG2N) of the block, bin e mod N)
+    R xt[PER];
+    double nm1[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = tid + t * NT;
+        xt[t] = (R)0;
+        nm1[t] = 0.0;
+        if (PER * NT == elems || e < elems) {
+            const int col = e >> LOG2N, ip = e & nmask;
+            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
+            xt[t] = img[(size_t)i * n + j] * inv_taper[i] * inv_taper[j];
+            const double l = (double)(j - hn) * g.pixel, m = (double)(i - hn) * g.pixel;
+            const double r2 = m * m + l * l;
+            nm1[t] = -r2 / (1.0 + sqrt(1.0 - r2));
+        }
+    }
+    const double w_lo = sc[c].w_lo, dw = sc[c].dw;
+    for (int k = 0; k < g.nw; ++k) {
+        if (!pocc[k]) continue;
+        double wk;
+        {
+#pragma clang fp contract(off)
+            wk = w_lo + ((double)k + 0.5) * dw;
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = tid + t * NT;
+            if (PER * NT == elems || e < elems) {
+                double cyc = wk * nm1[t];
+                cyc -= rint(cyc);
+                R sn, cs;
+                if constexpr (sizeof(R) == 4) {
+                    const float tt = (float)cyc;
+                    sn = __builtin_amdgcn_sinf(tt);
+                    cs = __builtin_amdgcn_cosf(tt);
+                } else {
+                    sincos_turn(cyc, &sn, &cs);
+                }
+                // conj(X_t exp(-2 pi i cyc)) = X_t (cos, +sin)
+                lds[lds_pad(e)] = cmake<C>(xt[t] * cs, xt[t] * sn);
+            }
+        }
+        __syncthreads();
+        fft_rows_lds<LOG2N, LR, B, NT>(lds, tw);
+        C* dst = inter + ((size_t)(c * g.nw + k) << (2 * LOG2N)) + (size_t)jb * elems;
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int f = tid + t * NT;       // [p'][col] order: contiguous in the intermediate
+            if (PER * NT == elems || f < elems) {
+                const int pp = f >> LOG2B, col = f & (B - 1);
+                const int p = (pp + hn) & nmask;
+                if (socc[k * g.S + (p >> g.log2H)]) {
+                    const C v = lds[lds_pad((col << LOG2N) + pp)];
+                    dst[f] = cmake<C>(v.x, -v.y);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One occupied strip (plane k of channel c, strip s): its rows of the intermediate, the row
+// transform (- sign, as above) in LDS, then every record whose taps reach the strip reads
+// them and adds its partial sum to its visibility.
+template <typename R, int LOG2N, int WMAX>
+__device__ __forceinline__ void degrid_strip(const Geom& g, int c, int k, int s, unsigned char* smem_raw,
+                                             const uint32_t* __restrict__ offsets,
+                                             const uint32_t* __restrict__ rec_cell,
+                                             const void* __restrict__ rec,
+                                             const uint32_t* __restrict__ rec_idx,
+                                             const R* __restrict__ kbc,
+                                             const typename Cx<R>::T* __restrict__ tw,
+                                             const typename Cx<R>::T* __restrict__ inter,
+                                             typename Cx<R>::T* __restrict__ vis_out) {
+    using C = typename Cx<R>::T;
+    using SH = Shape<R, LOG2N>;
+    constexpr int n = SH::N, H = SH::H, NT = SH::NT1, nmask = n - 1, hn = n >> 1;
+    constexpr int LOG2H = Log2Of<H>::value_any;
+    constexpr int B = SH::B, LOG2B = Log2Of<B>::value_any;
+    constexpr int elems = H * n;
+    constexpr int LHB = LOG2H + LOG2B;
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int row0 = s * H;
+    const int pp0 = (row0 + hn) & nmask;        // a strip never wraps in p' (H divides N/2)
+    const C* src = inter + ((size_t)(c * g.nw + k) << (2 * LOG2N));
+    for (int e = tid; e < elems; e += NT) {
+        const int jb = e >> LHB, rem = e & ((1 << LHB) - 1);
+        const int lr = rem >> LOG2B, col = rem & (B - 1);
+        const int j = (jb << LOG2B) + col;
+        const C v = src[((size_t)jb << LOG2N) * B + (size_t)(pp0 + lr) * B + col];
+        lds[lds_pad((lr << LOG2N) + ((j + hn) & nmask))] = cmake<C>(v.x, -v.y);
+    }
+    __syncthreads();
+    fft_rows_lds<LOG2N, SH::LR1, H, NT>(lds, tw);
+
+    const int W = g.support;
+    int s_lo = (row0 - (W - 1)) >> LOG2H;
+    if (s_lo < 0) s_lo = 0;
+    const int bucket0 = c * g.nb1 + k * g.S;
+    for (int sp = s_lo; sp <= s; ++sp) {
+        const uint32_t beg = offsets[(size_t)(bucket0 + sp) << kLogReplicas];
+        const uint32_t end = offsets[(size_t)(bucket0 + sp + 1) << kLogReplicas];
+        for (uint32_t r = beg + tid; r < end; r += NT) {
+            int q0, p0;
+            C fr, v;
+            decode_record<R>(fetch_record<R>(rec_cell, rec, r), sp, LOG2H, q0, p0, fr, v);
+            int b_lo = row0 - p0;
+            if (b_lo < 0) b_lo = 0;
+            int b_hi = row0 + H - 1 - p0;
+            if (b_hi > W - 1) b_hi = W - 1;
+            if (b_lo > b_hi) continue;
+            R gx[WMAX];
+#pragma unroll
+            for (int a = 0; a < WMAX; ++a)
+                if (a < W) gx[a] = kb_tap<R>(kbc, a, fr.x);
+            R sr = (R)0, si = (R)0;
+            for (int b = b_lo; b <= b_hi; ++b) {
+                const R gy = kb_tap<R>(kbc, b, fr.y);
+                const int lrow = (p0 + b - row0) << LOG2N;
+                R tr = (R)0, ti = (R)0;
+#pragma unroll
+                for (int a = 0; a < WMAX; ++a) {
+                    if (a < W) {
+                        const C h = lds[lds_pad(lrow + ((q0 + a + hn) & nmask))];
+                        tr += gx[a] * h.x;
+                        ti -= gx[a] * h.y;      // the conjugate undoes the transform's conjugation
+                    }
+                }
+                sr += gy * tr;
+                si += gy * ti;
+            }
+            const uint32_t m = rec_idx[r];
+            unsafeAtomicAdd(&vis_out[m].x, sr);
+            unsafeAtomicAdd(&vis_out[m].y, si);
+        }
+    }
+}
+
+// Persistent over the work list of occupied strips of all channels (as k_grid_rows).
+template <typename R, int LOG2N, int WMAX>
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
+k_adj_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
+           const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
+           const void* __restrict__ rec, const uint32_t* __restrict__ rec_idx, const R* __restrict__ kbc,
+           const typename Cx<R>::T* __restrict__ tw, const typename Cx<R>::T* __restrict__ inter,
+           typename Cx<R>::T* __restrict__ vis_out) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int item;
+    const int total = nch * g.nb1;
+    const unsigned n_heavy = wl->n_heavy, n_light = wl->n_light;
+    while (true) {
+        if (threadIdx.x == 0) {
+            const unsigned i = atomicAdd(&wl->next, 1u);
+            int b = -1;
+            if (i < n_heavy) b = (int)list[i];
+            else if (i - n_heavy < n_light) b = (int)list[total - 1 - (int)(i - n_heavy)];
+            item = b;
+        }
+        __syncthreads();
+        const int b = item;
+        __syncthreads();
+        if (b < 0) break;
+        const int c = b / g.nb1, bb = b - c * g.nb1;
+        const int k = bb / g.S, s = bb - k * g.S;
+        degrid_strip<R, LOG2N, WMAX>(g, c, k, s, smem_raw, offsets, rec_cell, rec, rec_idx, kbc,
+                                     opaque_ptr(tw), inter, vis_out);
+        __syncthreads();
     }
 }
 

@@ -68,6 +68,7 @@ struct wsimg_plan {
     uint32_t* list = nullptr;      // work list of occupied strips
     int persist_blocks = 256;      // work-groups of the persistent gridding kernel
     uint32_t *key = nullptr, *rank = nullptr, *rec_cell = nullptr, *rec_cell2 = nullptr;
+    uint32_t* rec_idx = nullptr;   // input row of each record (prediction)
     void *rec = nullptr, *rec2 = nullptr, *inter = nullptr;   // records by bucket; by (bucket, origin)
     void *tw = nullptr, *inv_taper = nullptr, *kbc = nullptr;
     int64_t device_bytes = 0;
@@ -134,7 +135,7 @@ wsimg_status validate_params(const wsimg_params* p, int64_t max_vis) {
     if (!(2.0 * lmax * lmax < 1.0))
         return fail(WSIMG_E_INVALID, "field too wide: a corner pixel has l^2 + m^2 >= 1");
     if (!std::isfinite(p->beta)) return fail(WSIMG_E_INVALID, "beta must be finite");
-    if (p->reserved != 0 || (p->flags & ~WSIMG_FIXED_WRANGE) != 0)
+    if (p->reserved != 0 || (p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED)) != 0)
         return fail(WSIMG_E_INVALID, "unknown flags or reserved field set");
     if (p->flags & WSIMG_FIXED_WRANGE) {
         if (!std::isfinite(p->w_lo) || !std::isfinite(p->w_hi) || p->w_lo > p->w_hi)
@@ -188,6 +189,13 @@ wsimg_status configure_shape(wsimg_plan* pl) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
+    WS_HIP(hipFuncSetAttribute((const void*)k_adj_cols<R, LOG2N>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
+    const int lds_adj = (int)(SH::LDS1 * sizeof(typename Cx<R>::T));
+    WS_HIP(hipFuncSetAttribute((const void*)k_adj_rows<R, LOG2N, 7>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_adj));
+    WS_HIP(hipFuncSetAttribute((const void*)k_adj_rows<R, LOG2N, kMaxSupport>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_adj));
     return WSIMG_OK;
 }
 
@@ -255,6 +263,35 @@ template <typename R> wsimg_status grid_rows(wsimg_plan* pl, int nch, bool fft, 
 }
 template <typename R> wsimg_status cols_stack(wsimg_plan* pl, int nch, void* image) {
     WS_SIZE_DISPATCH(R, pl->g.log2n, launch_cols, pl, nch, image)
+}
+
+// Prediction: column pass (image -> intermediate), then the persistent row pass + degridding.
+template <typename R, int LOG2N, int WMAX>
+wsimg_status launch_adj_rows_w(wsimg_plan* pl, int nch, void* vis_out) {
+    using C = typename Cx<R>::T;
+    const size_t lds = (size_t)Shape<R, LOG2N>::LDS1 * sizeof(C);
+    hipLaunchKernelGGL((k_adj_rows<R, LOG2N, WMAX>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1), lds,
+                       pl->stream, pl->g, nch, pl->worklist, pl->list, pl->offsets, pl->rec_cell,
+                       (const void*)pl->rec, (const uint32_t*)pl->rec_idx, (const R*)pl->kbc,
+                       (const C*)pl->tw, (const C*)pl->inter, (C*)vis_out);
+    WS_LAUNCH_CHECK("adj_rows");
+    return WSIMG_OK;
+}
+
+template <typename R, int LOG2N>
+wsimg_status launch_predict(wsimg_plan* pl, int nch, const void* image, void* vis_out) {
+    using C = typename Cx<R>::T;
+    const Geom g = pl->g;
+    hipLaunchKernelGGL((k_adj_cols<R, LOG2N>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2), pl->lds2,
+                       pl->stream, g, pl->scalars, pl->occ, pl->plane_occ, (const R*)image, (const C*)pl->tw,
+                       (const R*)pl->inv_taper, (C*)pl->inter);
+    WS_LAUNCH_CHECK("adj_cols");
+    return g.support <= 7 ? launch_adj_rows_w<R, LOG2N, 7>(pl, nch, vis_out)
+                          : launch_adj_rows_w<R, LOG2N, kMaxSupport>(pl, nch, vis_out);
+}
+
+template <typename R> wsimg_status predict_passes(wsimg_plan* pl, int nch, const void* image, void* vis_out) {
+    WS_SIZE_DISPATCH(R, pl->g.log2n, launch_predict, pl, nch, image, vis_out)
 }
 
 // A call's channels: counts and frequencies as passed (host), with their totals.
@@ -332,9 +369,12 @@ inline unsigned blocks_for(int64_t count, int threads) {
 }
 
 // Stages shared by wsimg_image and wsimg_grid: counters, plane ranges, bucket sort.
+// vis == nullptr: the sort for a prediction (records carry positions and their input rows,
+// and need no origin order).
 template <typename R>
 wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* uvw, const void* vis,
                       const void* wts) {
+    const bool predict = vis == nullptr;
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
     hipStream_t s = pl->stream;
@@ -383,12 +423,12 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     if (M > 0) {
         hipLaunchKernelGGL((k_scatter<R, R>), dim3(blocks_for(M, 256), nch), dim3(256), 0, s, ch, uvw,
                            (const C*)vis, (const R*)wts, g, pl->key, pl->rank, pl->offsets,
-                           pl->rec_cell, pl->rec);
+                           pl->rec_cell, pl->rec, predict ? pl->rec_idx : nullptr);
         WS_LAUNCH_CHECK("scatter");
     }
     if (auto r = st.after(4)) return r;
 
-    if (M > 0) {
+    if (M > 0 && !predict) {
         hipLaunchKernelGGL((k_origin_sort<R>), dim3((unsigned)pl->nb, nch), dim3(kSortThreads), 0, s, g,
                            pl->offsets, pl->rec_cell, (const void*)pl->rec, pl->rec_cell2, pl->rec2);
         WS_LAUNCH_CHECK("origin_sort");
@@ -416,7 +456,7 @@ wsimg_status run_image(wsimg_plan* pl, const Batch& bt, const double* uvw, const
     return WSIMG_OK;
 }
 
-wsimg_status finish_call(wsimg_plan* pl, int nch, wsimg_stats* stats) {
+wsimg_status finish_call(wsimg_plan* pl, int nch, wsimg_stats* stats, bool empty_is_error = true) {
     if (!stats) return WSIMG_OK;
     std::vector<Scalars> h((size_t)nch);
     WS_HIP(hipMemcpyAsync(h.data(), pl->scalars, sizeof(Scalars) * nch, hipMemcpyDeviceToHost, pl->stream));
@@ -434,7 +474,7 @@ wsimg_status finish_call(wsimg_plan* pl, int nch, wsimg_stats* stats) {
         o.n_planes_occupied = (int64_t)h[c].n_planes;
         if (!(h[c].sum_w != 0.0)) empty = true;
     }
-    if (empty) return fail(WSIMG_E_EMPTY, "the kept visibilities of a channel have zero total weight");
+    if (empty && empty_is_error) return fail(WSIMG_E_EMPTY, "the kept visibilities of a channel have zero total weight");
     return WSIMG_OK;
 }
 
@@ -448,6 +488,39 @@ wsimg_status dispatch(wsimg_plan* pl, int nch, const int64_t* counts, const doub
                          : run_image<double>(pl, bt, uvw, vis, wts, out, grid_only);
     if (r) return r;
     return finish_call(pl, nch, stats);
+}
+
+template <typename R>
+wsimg_status run_predict(wsimg_plan* pl, const Batch& bt, const double* uvw, const void* wts, const void* image,
+                         void* vis_out) {
+    Stamp st(pl);
+    if (auto r = st.begin()) return r;
+    if (auto r = run_sort<R>(pl, st, bt, uvw, nullptr, wts)) return r;
+    const int64_t words = bt.total * (int64_t)(2 * sizeof(R) / 4);
+    if (words > 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(std::min<int64_t>(blocks_for(words, 256), 8192)), dim3(256), 0,
+                           pl->stream, (uint32_t*)vis_out, words, 0u);
+        WS_LAUNCH_CHECK("zero visibilities");
+    }
+    if (auto r = st.after(5)) return r;
+    if (bt.total > 0) {
+        if (auto r = predict_passes<R>(pl, bt.nch, image, vis_out)) return r;
+    }
+    if (auto r = st.after(6)) return r;
+    if (auto r = st.after(7)) return r;
+    return WSIMG_OK;
+}
+
+wsimg_status dispatch_predict(wsimg_plan* pl, int64_t n_vis, const double* uvw, const void* wts, double freq,
+                              const void* image, void* vis_out, wsimg_stats* stats) {
+    Batch bt;
+    if (auto r = validate_call(pl, 1, &n_vis, &freq, uvw, wts, wts, vis_out, bt)) return r;
+    if (!image) return fail(WSIMG_E_INVALID, "image pointer is NULL");
+    WS_HIP(hipSetDevice(pl->device));
+    wsimg_status r = pl->p.precision == WSIMG_F32 ? run_predict<float>(pl, bt, uvw, wts, image, vis_out)
+                                                  : run_predict<double>(pl, bt, uvw, wts, image, vis_out);
+    if (r) return r;
+    return finish_call(pl, 1, stats, false);
 }
 
 wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, int max_channels,
@@ -476,6 +549,7 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     g.half_n = (double)n / 2.0;
     g.pixel = p->pixel_rad;
     g.fixed_range = (p->flags & WSIMG_FIXED_WRANGE) ? 1 : 0;
+    g.unnormalized = (p->flags & WSIMG_UNNORMALIZED) ? 1 : 0;
     g.w_lo_fixed = p->w_lo; g.w_hi_fixed = p->w_hi;
     {
         wsimg_status rs = f32 ? configure<float>(pl) : configure<double>(pl);
@@ -522,6 +596,7 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * mv, "record cells");
     ALLOC(rec, (f32 ? 16 : 32) * mv, "records");
     ALLOC(rec_cell2, f32 ? 256 : sizeof(uint32_t) * mv, "record cells by origin");
+    ALLOC(rec_idx, sizeof(uint32_t) * mv, "record rows");
     ALLOC(rec2, (f32 ? 16 : 32) * mv, "records by origin");
     ALLOC(inter, pl->cbytes * cells * mc, "row-transformed planes");
     ALLOC(tw, pl->cbytes * n, "twiddles");
@@ -616,6 +691,11 @@ wsimg_status wsimg_image_batch(wsimg_plan* plan, int32_t n_channels, const int64
                                const double* uvw_m, const void* vis, const void* weights,
                                const double* freqs_hz, void* images_out, wsimg_stats* stats) {
     return dispatch(plan, n_channels, row_counts, uvw_m, vis, weights, freqs_hz, images_out, stats, false);
+}
+
+wsimg_status wsimg_predict(wsimg_plan* plan, int64_t n_vis, const double* uvw_m, const void* weights,
+                           double freq_hz, const void* image_in, void* vis_out, wsimg_stats* stats) {
+    return dispatch_predict(plan, n_vis, uvw_m, weights, freq_hz, image_in, vis_out, stats);
 }
 
 wsimg_status wsimg_grid(wsimg_plan* plan, int64_t n_vis, const double* uvw_m, const void* vis,

@@ -15,6 +15,7 @@ from .interferometer import (  # noqa: F401
     make_config,
     make_channels,
     stack_channels,
+    sky_image,
     antenna_layout,
     baselines_xyz,
     uvw_track,

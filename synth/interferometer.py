@@ -340,3 +340,25 @@ def stack_channels(channels: List[Dataset]):
     counts = [int(c.uvw_m.shape[0]) for c in channels]
     freqs = [float(c.freq_hz) for c in channels]
     return uvw, vis, wts, counts, freqs
+
+
+def sky_image(ds: Dataset, field_amp: float = 0.05, field_sigma_frac: float = 0.125,
+              seed: int = 1105) -> np.ndarray:
+    """A dataset's sky as an [n, n] float64 image (row i: m = (i - n/2) dl; column j: l):
+    each source's flux at its nearest pixel, plus a smooth Gaussian field of peak field_amp
+    and width field_sigma_frac * n pixels at a seeded offset from the centre."""
+    n, dl = ds.n, ds.pixel_rad
+    img = np.zeros((n, n))
+    src = ds.sources
+    if src and len(src.get("l", [])):
+        j = np.rint(np.asarray(src["l"]) / dl + n // 2).astype(np.int64)
+        i = np.rint(np.asarray(src["m"]) / dl + n // 2).astype(np.int64)
+        ok = (i >= 0) & (i < n) & (j >= 0) & (j < n)
+        np.add.at(img, (i[ok], j[ok]), np.asarray(src["flux"])[ok])
+    rng = np.random.default_rng(seed)
+    ci, cj = n // 2 + rng.uniform(-0.1, 0.1, 2) * n
+    sig = field_sigma_frac * n
+    ii = np.arange(n)[:, None]
+    jj = np.arange(n)[None, :]
+    img += field_amp * np.exp(-((ii - ci) ** 2 + (jj - cj) ** 2) / (2.0 * sig * sig))
+    return img

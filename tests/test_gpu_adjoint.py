@@ -1,0 +1,166 @@
+"""The prediction operator (wsimg_predict) and the autograd operator built on it.
+
+* parity of the prediction with the oracle's (the transpose of its unnormalised imager),
+  float64 to 1e-12 and float32 to 1e-5 in relative L2 over the kept rows;
+* the dot-product test sum A(z) X = Re sum z conj(P X) on the GPU, with A the unnormalised
+  imager of the same library (float64 to 1e-12, float32 to 1e-5);
+* the gradient of a weighted chi-square through ImagingOperator: against central finite
+  differences on 32 random pixels (float64; the loss is quadratic in X, so the central
+  difference is exact up to rounding) and against the oracle's gradient
+  2 A(w (P X - V)) over the whole image.
+The differentiable-operator workload: 2048^2 sky image (50 points and a smooth Gaussian
+field), 4 M visibilities of the MeerKAT-shaped array, 16 w-planes, support 7, noise 1e-2.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import _prm, _random_ds, _torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_predict_parity_c1(oracle_mod, c1, prec):
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision(prec)
+    rng = np.random.default_rng(41)
+    X = rng.normal(size=(ds.n, ds.n))
+    rdt = np.float32 if prec == "f32" else np.float64
+    y, st = ws.predict(_t(torch, ds.uvw_m), _t(torch, ds.weights), ds.freq_hz, _t(torch, X.astype(rdt)),
+                       pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta,
+                       stats=True)
+    y = y.cpu().numpy().astype(np.complex128)
+    d64 = c1.as_precision("f64")
+    pr = oracle_mod.prepare(d64.uvw_m, d64.weights, d64.freq_hz, _prm(oracle_mod, d64))
+    ref = oracle_mod.wstack_predict(d64.uvw_m, d64.weights, d64.freq_hz, _prm(oracle_mod, d64),
+                                    X.astype(rdt).astype(np.float64), prepared=pr)
+    assert st["n_gridded"] == pr.n_kept and st["w_lo"] == pr.w_lo and st["w_hi"] == pr.w_hi
+    assert np.all(y[~pr.keep] == 0)
+    err = _rel(y[pr.keep], ref[pr.keep])
+    print(f"predict c1 {prec}: rel L2 {err:.3e}")
+    assert err <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,nw,W,m", [(16, 1, 3, 40), (64, 3, 15, 3000), (256, 4, 9, 20000), (1024, 3, 7, 50000)])
+def test_predict_parity_shapes(oracle_mod, prec, n, nw, W, m):
+    """The prediction divides the image by C(xi_i) C(xi_j) first, which amplifies the edge
+    pixels by up to C(0)^2 / C(1/2)^2 (2.6e3 for W = 7, 4.3e7 for W = 15), and the taps then
+    cancel that amplification again: rounding grows by the same factor, as in the imager.
+    So the tolerance is checked on a tapered image (X = C(xi_i) C(xi_j) / C(0)^2 x noise,
+    no amplification) at every support, and on a raw noise image where W <= 7."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    from helpers import _taper
+    ds = _random_ds(300 + n + W, m, n, nw, W, prec)
+    rng = np.random.default_rng(n + nw)
+    rdt = np.float32 if prec == "f32" else np.float64
+    d64 = ds.as_precision("f64")
+    t = _taper(oracle_mod, n, W, ds.beta)
+    raw = rng.normal(size=(n, n))
+    cases = [("tapered", raw * np.outer(t, t))] + ([("raw", raw)] if W <= 7 else [])
+    for tag, X in cases:
+        X = X.astype(rdt)
+        y = ws.predict(_t(torch, ds.uvw_m), _t(torch, ds.weights), ds.freq_hz, _t(torch, X),
+                       pixel_rad=ds.pixel_rad, n_wplanes=nw, support=W, beta=ds.beta).cpu().numpy()
+        ref = oracle_mod.wstack_predict(d64.uvw_m, d64.weights, d64.freq_hz, _prm(oracle_mod, d64),
+                                        X.astype(np.float64))
+        err = _rel(y.astype(np.complex128), ref)
+        print(f"predict n={n} nw={nw} W={W} {prec} {tag}: rel L2 {err:.3e}")
+        assert err <= (1e-12 if prec == "f64" else 1e-5), tag
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dot_product_on_gpu(c1, prec):
+    """sum_ij A(z)_ij X_ij = Re sum_m z_m conj((P X)_m), both sides from the library."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision(prec)
+    rng = np.random.default_rng(43)
+    cdt = np.complex64 if prec == "f32" else np.complex128
+    rdt = np.float32 if prec == "f32" else np.float64
+    z = (rng.normal(size=ds.m) + 1j * rng.normal(size=ds.m)).astype(cdt)
+    X = rng.normal(size=(ds.n, ds.n)).astype(rdt)
+    uvw, wts = _t(torch, ds.uvw_m), _t(torch, np.ones(ds.m, dtype=rdt))
+    op = ws.ImagingOperator(uvw, wts, ds.freq_hz, ds.n, ds.pixel_rad, ds.n_wplanes, ds.support, ds.beta,
+                            precision=prec)
+    Az = op.adjoint(_t(torch, z)).cpu().numpy().astype(np.float64)
+    PX = op.predict(_t(torch, X)).cpu().numpy().astype(np.complex128)
+    op.close()
+    lhs = float(np.sum(Az * X.astype(np.float64)))
+    rhs = float(np.real(np.sum(z.astype(np.complex128) * np.conj(PX))))
+    scale = float(np.linalg.norm(Az) * np.linalg.norm(X))
+    print(f"dot product {prec}: {lhs:.9e} vs {rhs:.9e} (|diff|/scale {abs(lhs - rhs) / scale:.2e})")
+    assert abs(lhs - rhs) <= (1e-12 if prec == "f64" else 1e-5) * scale
+
+
+@pytest.fixture(scope="module")
+def c5():
+    _torch()
+    import synth
+    ds = synth.make_config(5, device="cuda")
+    sky = synth.sky_image(ds)
+    return ds, sky
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_chi_square_gradient(oracle_mod, c5, prec):
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds0, sky = c5
+    ds = ds0.as_precision(prec)
+    rdt = torch.float32 if prec == "f32" else torch.float64
+    sigma = 1e-2
+    w = np.full(ds.m, 1.0 / sigma ** 2)
+    uvw = _t(torch, ds.uvw_m)
+    wt = _t(torch, w.astype(np.float32 if prec == "f32" else np.float64))
+    V = _t(torch, ds.vis)
+    op = ws.ImagingOperator(uvw, wt, ds.freq_hz, ds.n, ds.pixel_rad, ds.n_wplanes, ds.support, ds.beta,
+                            precision=prec)
+    X = torch.tensor(sky, dtype=rdt, device="cuda:0", requires_grad=True)
+
+    def loss_of(img):
+        r = op(img) - V
+        return (wt * (r.real ** 2 + r.imag ** 2)).sum()
+
+    L = loss_of(X)
+    L.backward()
+    g = X.grad.detach().cpu().numpy().astype(np.float64)
+
+    # the oracle's gradient: 2 A(w (P X - V)) with its own prediction and imager
+    d64 = ds0.as_precision("f64")
+    prm = _prm(oracle_mod, d64, w_range=op.w_range)
+    Xn = sky.astype(np.float32).astype(np.float64) if prec == "f32" else sky
+    r = oracle_mod.wstack_predict(d64.uvw_m, w, d64.freq_hz, prm, Xn) - ds.vis.astype(np.complex128)
+    g_ref = 2.0 * oracle_mod.wstack_image(d64.uvw_m, r, w, d64.freq_hz, prm, normalize=False)
+    err = _rel(g, g_ref)
+    print(f"chi-square gradient {prec}: rel L2 vs oracle {err:.3e}")
+    assert err <= (1e-10 if prec == "f64" else 1e-4)
+
+    if prec == "f64":
+        rng = np.random.default_rng(47)
+        n = ds.n
+        pix = rng.integers(n // 8, n - n // 8, size=(32, 2))
+        h = 1e-3
+        worst = 0.0
+        with torch.no_grad():
+            for i, j in pix:
+                Xp = X.detach().clone()
+                Xm = X.detach().clone()
+                Xp[i, j] += h
+                Xm[i, j] -= h
+                fd = (loss_of(Xp).item() - loss_of(Xm).item()) / (2 * h)
+                worst = max(worst, abs(fd - g[i, j]) / np.max(np.abs(g)))
+        print(f"finite differences on 32 pixels: worst |fd - grad| / max|grad| {worst:.2e}")
+        assert worst <= 1e-6
+    op.close()
