@@ -11,6 +11,10 @@ With --workload c4 a step is one call that images all 64 channels of the batched
 MeerKAT-shaped set (856-1712 MHz, 1024^2 images, 16 w-planes, 0-60 % random flagging per
 channel); the same channels imaged by 64 single-channel calls are timed beside it.
 
+With --workload c5 a step is one evaluation of a weighted chi-square data-fidelity loss and
+its gradient with respect to a 2048^2 sky image through the differentiable imaging operator
+(prediction of 4 M visibilities, then the transpose for the gradient), float32.
+
 Prints ONE JSON line.  Extra objects:
   roofline     : the dominant kernel's algorithmic bytes (or flops) per launch over its
                  average duration, from HIP events recorded on the plan's stream during
@@ -36,7 +40,7 @@ if ROOT not in sys.path:
 METRIC = "visibilities imaged/s (FP32 vs FP64 path, 1 GPU) at ≤1e-5 rel err vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector, published (includes packed issue)
-WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4}
+WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5}
 
 
 def log(*a):
@@ -232,6 +236,9 @@ def main():
     if cfg == 4:
         bench_batch(args)
         return
+    if cfg == 5:
+        bench_adjoint(args)
+        return
     t0 = time.perf_counter()
     ds = synth.make_config(cfg, device="cuda" if torch.cuda.is_available() else "cpu")
     log(f"generated {ds.name}: M={ds.m} n={ds.n} nw={ds.n_wplanes} W={ds.support} "
@@ -300,6 +307,68 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample of planes ...")
         res["cpu_baseline"] = cpu_baseline(ds, args.cpu_sample_planes)
+    print(json.dumps(res), flush=True)
+
+
+def bench_adjoint(args):
+    """The differentiable-operator workload: loss + gradient per step."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2601_19714_amd as ws
+
+    t0 = time.perf_counter()
+    ds = synth.make_config(5, device="cuda" if torch.cuda.is_available() else "cpu").as_precision("f32")
+    sky = synth.sky_image(ds)
+    log(f"generated {ds.name}: M={ds.m} n={ds.n} nw={ds.n_wplanes} in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    uvw = torch.from_numpy(ds.uvw_m).to(dev)
+    V = torch.from_numpy(ds.vis).to(dev)
+    w = torch.full((ds.m,), 1.0e4, dtype=torch.float32, device=dev)
+    op = ws.ImagingOperator(uvw, w, ds.freq_hz, ds.n, ds.pixel_rad, ds.n_wplanes, ds.support, ds.beta,
+                            precision="f32")
+    X = torch.tensor(sky, dtype=torch.float32, device=dev, requires_grad=True)
+
+    def step():
+        X.grad = None
+        r = op(X) - V
+        loss = (w * (r.real ** 2 + r.imag ** 2)).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup + 1):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    # the two directions alone
+    with torch.no_grad():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            y = op.predict(X.detach())
+        torch.cuda.synchronize()
+        ms_pred = 1e3 * (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            op.adjoint(y)
+        torch.cuda.synchronize()
+        ms_adj = 1e3 * (time.perf_counter() - t0) / args.steps
+    log(f"loss+gradient: {ms:.3f} ms/step; prediction {ms_pred:.3f} ms, transpose {ms_adj:.3f} ms")
+    res = {
+        "metric": "visibilities/s through loss + gradient (prediction and its transpose), 1 GPU",
+        "value": ds.m / (ms / 1e3), "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c5_adjoint_f32", "n_vis": ds.m, "n": ds.n, "n_wplanes": ds.n_wplanes,
+                   "support": ds.support, "precision": "f32"},
+        "ms_prediction": ms_pred, "ms_transpose": ms_adj,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    op.close()
     print(json.dumps(res), flush=True)
 
 

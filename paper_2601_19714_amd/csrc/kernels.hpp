@@ -573,7 +573,7 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
 #define WSIMG_F32_LR1 4
 #endif
 #ifndef WSIMG_F32_LR2
-#define WSIMG_F32_LR2 4
+#define WSIMG_F32_LR2 3
 #endif
 #ifndef WSIMG_F64_LR1
 #define WSIMG_F64_LR1 4
@@ -581,13 +581,18 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
 #ifndef WSIMG_F64_LR2
 #define WSIMG_F64_LR2 3
 #endif
-// cells of one gridding strip (H * N): its float64 accumulator takes 16 B per cell of LDS
+// cells of one gridding strip (H * N): its float64 accumulator takes 16 B per cell of LDS.
+// Images below 4096^2 use the smaller strip (two work-groups per CU, fewer walks per strip).
 #ifndef WSIMG_STRIP_CELLS
 #define WSIMG_STRIP_CELLS 8192
 #endif
-static_assert(WSIMG_STRIP_CELLS <= 8192, "origins of a strip index an 8192-bin histogram");
+#ifndef WSIMG_STRIP_CELLS_SMALL
+#define WSIMG_STRIP_CELLS_SMALL 4096
+#endif
+static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
+              "origins of a strip index an 8192-bin histogram");
 #ifndef WSIMG_F32_PX2
-#define WSIMG_F32_PX2 4096
+#define WSIMG_F32_PX2 8192
 #endif
 #ifndef WSIMG_F64_PX2
 #define WSIMG_F64_PX2 4096
@@ -606,7 +611,7 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int LR1 = LR1_0 < LOG2N ? LR1_0 : LOG2N - 1;
     static constexpr int LR2 = LR2_0 < LOG2N ? LR2_0 : LOG2N - 1;
     static constexpr int E1 = 1 << LR1, E2 = 1 << LR2;
-    static constexpr int CAP1 = WSIMG_STRIP_CELLS;
+    static constexpr int CAP1 = LOG2N >= 12 ? WSIMG_STRIP_CELLS : WSIMG_STRIP_CELLS_SMALL;
     static constexpr int H0 = CAP1 / N < 32 ? (CAP1 / N < 1 ? 1 : CAP1 / N) : 32;   // a row at least
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
     static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);
@@ -646,10 +651,15 @@ template <typename R, int LOG2N> struct Shape {
 #endif
 constexpr uint32_t kChunkMax = WSIMG_GRID_CHUNK_MAX;
 
-// Register rows per walk for a support class WMAX: the accumulators stay within 64 VGPRs.
+// Register rows per walk for a support class WMAX: the float64 run sums (4 VGPRs per tap)
+// stay within WSIMG_WALK_VGPRS registers.
+#ifndef WSIMG_WALK_VGPRS
+#define WSIMG_WALK_VGPRS 64
+#endif
 template <typename R, int WMAX> struct WalkRows {
     static constexpr int words = WMAX * 4;
-    static constexpr int value = 64 / words >= 4 ? 4 : (64 / words >= 2 ? 2 : 1);
+    static constexpr int fit = WSIMG_WALK_VGPRS / words;
+    static constexpr int value = fit >= 8 ? 8 : (fit >= 4 ? 4 : (fit >= 2 ? 2 : 1));
 };
 
 // One occupied strip (plane k of channel c, strip s) by the whole work-group.
@@ -868,7 +878,11 @@ k_grid_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restri
 //   * in float, the next plane's first-pass inputs are loaded while this plane is transformed.
 // At the end: divide by the taper on both axes and by the sum of weights.
 
-template <typename R> struct Pass2Prefetch { static constexpr bool value = sizeof(R) == 4; };
+// float: the next plane's first-pass inputs are loaded while this plane is transformed
+#ifndef WSIMG_COLS_PREFETCH
+#define WSIMG_COLS_PREFETCH 1
+#endif
+template <typename R> struct Pass2Prefetch { static constexpr bool value = sizeof(R) == 4 && WSIMG_COLS_PREFETCH; };
 
 template <typename R, int LOG2N, int LR, int B>
 __device__ __forceinline__ void pass2_load(const typename Cx<R>::T* __restrict__ src,
@@ -886,8 +900,14 @@ __device__ __forceinline__ void pass2_load(const typename Cx<R>::T* __restrict__
     }
 }
 
+// Waves per SIMD the stacking kernel is compiled for (0: the compiler's choice).  Asking for
+// more caps its registers so that two work-groups fit on a CU.
+#ifndef WSIMG_COLS_WAVES_PER_EU
+#define WSIMG_COLS_WAVES_PER_EU 0
+#endif
+
 template <typename R, int LOG2N>
-__global__ void __launch_bounds__((Shape<R, LOG2N>::NT2))
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT2), WSIMG_COLS_WAVES_PER_EU)
 k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ occ,
              const uint8_t* __restrict__ plane_occ, const typename Cx<R>::T* __restrict__ inter,
              const typename Cx<R>::T* __restrict__ tw, const R* __restrict__ inv_taper,
