@@ -138,6 +138,28 @@ def run_gpu_batch(chans, steps: int, warmup: int):
     info = plan.info()
     plan.close()
 
+    # the same call captured into a HIP graph and replayed
+    gplan = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, "f32", max_vis=sum(counts),
+                    max_channels=nch)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gplan.image_batch(uvw, vis, wts, counts, freqs, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gplan.image_batch(uvw, vis, wts, counts, freqs, out=out)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t0
+    del graph
+    gplan.close()
+
     off = np.concatenate([[0], np.cumsum(counts)])
     single = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, "f32", max_vis=max(counts))
     one = torch.empty((d.n, d.n), dtype=torch.float32, device=dev)
@@ -157,7 +179,8 @@ def run_gpu_batch(chans, steps: int, warmup: int):
     wall_single = time.perf_counter() - t0
     single.close()
     return {"ms_per_step": 1e3 * wall / steps, "timing": timing, "stats": st, "info": info,
-            "counts": counts, "ms_per_step_single_calls": 1e3 * wall_single / s_steps}
+            "counts": counts, "ms_per_step_single_calls": 1e3 * wall_single / s_steps,
+            "ms_per_step_graph": 1e3 * wall_graph / steps}
 
 
 def cpu_baseline(ds, n_sample_planes: int):
@@ -386,6 +409,7 @@ def bench_batch(args):
     m = sum(r["counts"])
     calls = max(1, r["timing"]["calls"])
     per_call = {k: v / calls for k, v in r["timing"]["ms"].items()}
+    log(f"graph replay: {r['ms_per_step_graph']:.3f} ms/step")
     log(f"batch: {r['ms_per_step']:.3f} ms/step ({len(chans)} channels), single calls "
         f"{r['ms_per_step_single_calls']:.3f} ms; stages(ms/call) " +
         ", ".join(f"{k}={v:.4f}" for k, v in per_call.items()))
@@ -418,6 +442,7 @@ def bench_batch(args):
                    "n_wplanes": d.n_wplanes, "support": d.support, "freq_hz": [chans[0].freq_hz, chans[-1].freq_hz],
                    "precision": "f32"},
         "per_channel_ms": r["ms_per_step"] / len(chans),
+        "ms_per_step_graph_replay": r["ms_per_step_graph"],
         "single_call_value": m / (r["ms_per_step_single_calls"] / 1e3),
         "batch_speedup_over_single_calls": r["ms_per_step_single_calls"] / r["ms_per_step"],
         "stage_ms": per_call,

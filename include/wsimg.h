@@ -20,6 +20,12 @@
  *  - Counts are int64_t (the paper's I/O section notes the 32-bit count limit of
  *    the MPI read calls; no count here is 32-bit).
  *  - A plan is not thread-safe; separate plans are independent.
+ *  - wsimg_image, wsimg_image_batch, wsimg_predict and wsimg_grid may be captured into a HIP
+ *    graph (stream capture of the plan's stream) when stats is NULL: under capture they make
+ *    no host wait, record no timing events, and read the channel table from a pinned buffer
+ *    that only captured calls write.  A replay recomputes the outputs from the current
+ *    contents of the inputs.  One captured call per plan at a time: capturing another call
+ *    on the same plan rewrites the table the earlier graph reads.
  *
  * Geometry (Sec. 2, Eq. 1): u, v, w are the baseline coordinates in wavelengths,
  * (u, v, w) = uvw_m * freq_hz / c with c = 299792458 m/s.  The image is n x n,

@@ -33,9 +33,21 @@ def flags(arch: str = "gfx950"):
     ]
 
 
+def tuned_flags():
+    """Macro definitions recorded by the autotuner (paper_2601_19714_amd/tune.py), if it ran."""
+    path = os.path.join(HERE, "tuned.json")
+    if not os.path.exists(path):
+        return []
+    import json
+    with open(path) as fh:
+        return list(json.load(fh).get("flags", []))
+
+
 def build(verbose: bool = False, extra=()) -> str:
+    """Compile libwsimg.so; the macro settings recorded by the autotuner (tuned.json), if any,
+    come first, then `extra`."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + list(extra) + [SRC, "-o", tmp]
+    cmd = [hipcc()] + flags() + tuned_flags() + list(extra) + [SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -63,6 +63,9 @@ struct wsimg_plan {
     void* staging = nullptr;
     hipEvent_t staged_ev = nullptr;
     bool staged_pending = false;
+    // a second pinned table for calls captured into a HIP graph: the graph's copy node reads
+    // it at every replay, so eager calls never write it
+    void* staging_graph = nullptr;
     uint32_t *counts = nullptr, *offsets = nullptr, *tile_sums = nullptr;
     uint8_t *occ = nullptr, *plane_occ = nullptr;
     uint32_t* list = nullptr;      // work list of occupied strips
@@ -103,6 +106,8 @@ void release(wsimg_plan* pl) {
     pl->allocations.clear();
     if (pl->staging) (void)hipHostFree(pl->staging);
     pl->staging = nullptr;
+    if (pl->staging_graph) (void)hipHostFree(pl->staging_graph);
+    pl->staging_graph = nullptr;
     if (pl->staged_ev) (void)hipEventDestroy(pl->staged_ev);
     pl->staged_ev = nullptr;
     for (auto& ev : pl->pending) for (auto e : ev) (void)hipEventDestroy(e);
@@ -324,19 +329,29 @@ wsimg_status validate_call(wsimg_plan* pl, int nch, const int64_t* counts, const
     return WSIMG_OK;
 }
 
+// True while the plan's stream is being captured into a HIP graph.
+bool capturing(const wsimg_plan* pl) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(pl->stream, &cs) != hipSuccess) return false;
+    return cs == hipStreamCaptureStatusActive;
+}
+
 // Channel table -> pinned staging -> device, on the plan's stream.  The staging buffer is
-// rewritten only after the device has copied the previous call's table.
+// rewritten only after the device has copied the previous call's table.  Under capture the
+// table goes to the graph's own buffer, with no host wait.
 wsimg_status upload_channels(wsimg_plan* pl, const Batch& bt) {
-    if (pl->staged_pending) {
+    const bool cap = capturing(pl);
+    if (!cap && pl->staged_pending) {
         WS_HIP(hipEventSynchronize(pl->staged_ev));
         pl->staged_pending = false;
     }
-    int64_t* ro = static_cast<int64_t*>(pl->staging);
+    int64_t* ro = static_cast<int64_t*>(cap ? pl->staging_graph : pl->staging);
     double* fq = reinterpret_cast<double*>(ro + (pl->max_channels + 1));
     ro[0] = 0;
     for (int c = 0; c < bt.nch; ++c) { ro[c + 1] = ro[c] + bt.counts[c]; fq[c] = bt.freqs[c]; }
     WS_HIP(hipMemcpyAsync(pl->row_off, ro, sizeof(int64_t) * (bt.nch + 1), hipMemcpyHostToDevice, pl->stream));
     WS_HIP(hipMemcpyAsync(pl->freq, fq, sizeof(double) * bt.nch, hipMemcpyHostToDevice, pl->stream));
+    if (cap) return WSIMG_OK;
     WS_HIP(hipEventRecord(pl->staged_ev, pl->stream));
     pl->staged_pending = true;
     return WSIMG_OK;
@@ -347,7 +362,7 @@ struct Stamp {
     std::array<hipEvent_t, WSIMG_N_KERNELS + 1>* ev = nullptr;
     explicit Stamp(wsimg_plan* p) : pl(p) {}
     wsimg_status begin() {
-        if (!pl->timing) return WSIMG_OK;
+        if (!pl->timing || capturing(pl)) return WSIMG_OK;
         std::array<hipEvent_t, WSIMG_N_KERNELS + 1> e{};
         if (!pl->spare.empty()) { e = pl->spare.back(); pl->spare.pop_back(); }
         else for (auto& x : e) WS_HIP(hipEventCreate(&x));
@@ -482,6 +497,7 @@ wsimg_status dispatch(wsimg_plan* pl, int nch, const int64_t* counts, const doub
                       const void* wts, const double* freqs, void* out, wsimg_stats* stats, bool grid_only) {
     Batch bt;
     if (auto r = validate_call(pl, nch, counts, freqs, uvw, vis, wts, out, bt)) return r;
+    if (stats && capturing(pl)) return fail(WSIMG_E_INVALID, "stats need a host wait: not under graph capture");
     WS_HIP(hipSetDevice(pl->device));
     wsimg_status r = pl->p.precision == WSIMG_F32
                          ? run_image<float>(pl, bt, uvw, vis, wts, out, grid_only)
@@ -516,6 +532,7 @@ wsimg_status dispatch_predict(wsimg_plan* pl, int64_t n_vis, const double* uvw, 
     Batch bt;
     if (auto r = validate_call(pl, 1, &n_vis, &freq, uvw, wts, wts, vis_out, bt)) return r;
     if (!image) return fail(WSIMG_E_INVALID, "image pointer is NULL");
+    if (stats && capturing(pl)) return fail(WSIMG_E_INVALID, "stats need a host wait: not under graph capture");
     WS_HIP(hipSetDevice(pl->device));
     wsimg_status r = pl->p.precision == WSIMG_F32 ? run_predict<float>(pl, bt, uvw, wts, image, vis_out)
                                                   : run_predict<double>(pl, bt, uvw, wts, image, vis_out);
@@ -604,9 +621,13 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     ALLOC(kbc, pl->rbytes * (size_t)p->support * 17, "kernel polynomials");
 #undef ALLOC
     if (!r) {
-        hipError_t e = hipHostMalloc(&pl->staging, sizeof(int64_t) * (mc + 1) + sizeof(double) * mc,
-                                     hipHostMallocDefault);
+        const size_t tb = sizeof(int64_t) * (mc + 1) + sizeof(double) * mc;
+        hipError_t e = hipHostMalloc(&pl->staging, tb, hipHostMallocDefault);
         if (e != hipSuccess) { pl->staging = nullptr; r = fail(WSIMG_E_NOMEM, "hipHostMalloc(channel table) failed"); }
+        if (!r) {
+            e = hipHostMalloc(&pl->staging_graph, tb, hipHostMallocDefault);
+            if (e != hipSuccess) { pl->staging_graph = nullptr; r = fail(WSIMG_E_NOMEM, "hipHostMalloc(graph table) failed"); }
+        }
     }
     if (!r) {
         hipError_t e = hipEventCreateWithFlags(&pl->staged_ev, hipEventDisableTiming);

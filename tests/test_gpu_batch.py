@@ -127,3 +127,40 @@ def test_batch_edge_cases(oracle_mod):
         with pytest.raises(ws.WsimgError) as ei:
             p.image_batch(u, v, w, counts, freqs)
         assert ei.value.status == -5                                   # total rows > max_vis
+
+
+def test_batch_graph_capture_and_replay(c4, c4_images):
+    """The 64-channel call captured into a HIP graph (torch.cuda.graph over the plan's
+    stream) and replayed three times, with eager calls on the same plan and host
+    synchronisations between the replays: every replay matches the eager images."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    chans, (u, v, w), counts, freqs = c4
+    eager, _, _ = c4_images
+    ds = chans[0]
+    with ws.Plan(ds.n, ds.pixel_rad, ds.n_wplanes, ds.support, ds.beta, "f32", max_vis=sum(counts),
+                 max_channels=len(counts)) as p:
+        out = torch.empty((len(counts), ds.n, ds.n), dtype=torch.float32, device="cuda:0")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            p.image_batch(u, v, w, counts, freqs, out=out)          # warm-up off the capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            p.image_batch(u, v, w, counts, freqs, out=out)
+        scale = np.max(np.abs(eager))
+        for rep in range(3):
+            out.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            err = float(np.max(np.abs(got - eager)) / scale)
+            print(f"replay {rep}: peak-relative difference from eager {err:.2e}")
+            assert err <= 1e-6, rep
+            # eager work on the same plan between replays (other channel counts)
+            half = sum(counts[:32])
+            p.image_batch(u[:half], v[:half], w[:half], counts[:32], freqs[:32])
+            torch.cuda.synchronize()
