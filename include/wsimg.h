@@ -64,6 +64,10 @@ typedef enum {
 #define WSIMG_UNNORMALIZED 0x2u   /* wsimg_image does not divide by the sum of weights:
                                      the image is then A(W V), the imaging operator that
                                      wsimg_predict is the transpose of                    */
+#define WSIMG_FOLD_W 0x4u         /* w-folding: a row with w < 0 is taken as its conjugate
+                                     partner (-u, -v, -w, conj V) (equal for a real sky),
+                                     so the planes span |w| only; the real image is the same
+                                     sum with half the w range per plane                  */
 
 typedef struct {
     int32_t n;          /* image side = grid side: a power of two, 16..8192 (16384 is

@@ -47,6 +47,7 @@ class Params:
     beta: float
     w_lo: Optional[float] = None    # both None: the range comes from the data
     w_hi: Optional[float] = None
+    fold: bool = False              # w-folding: a row with w < 0 is imaged as its conjugate partner
 
 
 @dataclasses.dataclass
@@ -65,6 +66,7 @@ class Prepared:
     w_hi: float
     dw: float
     sum_w: float
+    flip: Optional[np.ndarray] = None   # rows replaced by their conjugate partner (fold)
 
     @property
     def n_kept(self) -> int:
@@ -79,6 +81,13 @@ def prepare(uvw_m: np.ndarray, weights: np.ndarray, freq_hz: float, prm: Params)
     u = uvw_m[:, 0] * freq_hz / C_LIGHT
     v = uvw_m[:, 1] * freq_hz / C_LIGHT
     w = uvw_m[:, 2] * freq_hz / C_LIGHT
+    flip = np.zeros(u.shape[0], dtype=bool)
+    if prm.fold:
+        # w-folding: V(-u, -v, -w) = conj V(u, v, w) for a real sky, so a row with w < 0 is
+        # replaced by (-u, -v, -w, conj V); the planes then span |w| only
+        with np.errstate(invalid="ignore"):
+            flip = uvw_m[:, 2] < 0
+        u, v, w = np.where(flip, -u, u), np.where(flip, -v, v), np.where(flip, -w, w)
     du = 1.0 / (n * prm.pixel_rad)
     x = u / du + n / 2
     y = v / du + n / 2
@@ -108,7 +117,7 @@ def prepare(uvw_m: np.ndarray, weights: np.ndarray, freq_hz: float, prm: Params)
         kf = np.where(keep, kf, 0)
         k = np.clip(kf, 0, prm.n_wplanes - 1).astype(np.int64)
     sum_w = float(wt[keep].sum())
-    return Prepared(u, v, w, x, y, q0, p0, keep, k, w_lo, w_hi, dw, sum_w)
+    return Prepared(u, v, w, x, y, q0, p0, keep, k, w_lo, w_hi, dw, sum_w, flip)
 
 
 def tap_weights(pr: Prepared, prm: Params, rows: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
@@ -130,7 +139,10 @@ def grid_plane(pr: Prepared, vis: np.ndarray, weights: np.ndarray, prm: Params, 
     L = _lib()
     for c0 in range(0, rows.size, chunk):
         r = rows[c0:c0 + chunk]
-        wv = wt[r] * vis[r].astype(np.complex128)
+        vr = vis[r].astype(np.complex128)
+        if pr.flip is not None:
+            vr = np.where(pr.flip[r], np.conj(vr), vr)
+        wv = wt[r] * vr
         wv_re = np.ascontiguousarray(wv.real)
         wv_im = np.ascontiguousarray(wv.imag)
         gx, gy = tap_weights(pr, prm, r)
@@ -279,4 +291,6 @@ def wstack_predict(uvw_m, weights, freq_hz: float, prm: Params, image: np.ndarra
         L.oracle_degrid(n, prm.support, sel.size, _ptr(p0), _ptr(q0), _ptr(gx), _ptr(gy), _ptr(gri),
                         _ptr(res))
         out[sel] = res[:, 0] + 1j * res[:, 1]
+    if pr.flip is not None:
+        out = np.where(pr.flip, np.conj(out), out)     # the transpose of gridding conj(z)
     return out

@@ -53,7 +53,7 @@ class Plan:
     def __init__(self, n: int, pixel_rad: float, n_wplanes: int, support: int = 7,
                  beta: Optional[float] = None, precision: str = "f32", max_vis: int = 0,
                  w_range: Optional[Tuple[float, float]] = None, device=None, max_channels: int = 1,
-                 normalize: bool = True):
+                 normalize: bool = True, fold_w: bool = False):
         import torch
 
         self._torch = torch
@@ -72,6 +72,8 @@ class Plan:
             p.flags |= _lib.WSIMG_FIXED_WRANGE
         if not normalize:
             p.flags |= _lib.WSIMG_UNNORMALIZED
+        if fold_w:
+            p.flags |= _lib.WSIMG_FOLD_W
         self._L = _lib.load()
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

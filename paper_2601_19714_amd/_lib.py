@@ -19,6 +19,7 @@ WSIMG_F32 = 1
 WSIMG_F64 = 2
 WSIMG_FIXED_WRANGE = 0x1
 WSIMG_UNNORMALIZED = 0x2
+WSIMG_FOLD_W = 0x4
 WSIMG_N_KERNELS = 8
 
 # every symbol include/wsimg.h declares

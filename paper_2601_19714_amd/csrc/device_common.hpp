@@ -50,13 +50,19 @@ struct RowGeom {
     double x, y, w;
     double cx, cy;    // floor(x + 1/2), floor(y + 1/2): the cell nearest to the row
     bool keep;        // finite uvw and weight, all taps on the grid
+    bool flip;        // w-folding replaced the row by its conjugate partner
 };
 
+// fold: w-folding, a row with w < 0 becomes (-u, -v, -w) (its visibility is conjugated by the
+// caller): V(-u, -v, -w) = conj V(u, v, w) for a real sky, and the planes span |w| only.
 __device__ __forceinline__ RowGeom row_geometry(const double* __restrict__ uvw, int64_t m, double freq,
-                                                double du, double half_n, double wt, int n, int support) {
+                                                double du, double half_n, double wt, int n, int support,
+                                                bool fold) {
 #pragma clang fp contract(off)
     RowGeom g;
-    const double uu = uvw[3 * m + 0], vv = uvw[3 * m + 1], ww = uvw[3 * m + 2];
+    double uu = uvw[3 * m + 0], vv = uvw[3 * m + 1], ww = uvw[3 * m + 2];
+    g.flip = fold && ww < 0.0;
+    if (g.flip) { uu = -uu; vv = -vv; ww = -ww; }
     const double u = uu * freq / kCLight;
     const double v = vv * freq / kCLight;
     g.w = ww * freq / kCLight;

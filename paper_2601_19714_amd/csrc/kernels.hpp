@@ -38,6 +38,7 @@ struct Geom {
     int B, log2B, NB;       // image columns per stacking block, blocks
     int fixed_range;
     int unnormalized;       // the image is not divided by the sum of weights
+    int fold_w;             // w-folding (rows with w < 0 as their conjugate partners)
     double du, half_n, pixel;
     double w_lo_fixed, w_hi_fixed;
 };
@@ -115,7 +116,7 @@ k_reduce(Chan ch, int64_t chunk, int nparts, const double* __restrict__ uvw, con
     unsigned long long nk = 0;
     for (int64_t m = beg + threadIdx.x; m < end; m += blockDim.x) {
         const double wt = (double)wts[m];
-        RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support);
+        RowGeom rg = row_geometry(uvw, m, freq, g.du, g.half_n, wt, g.n, g.support, g.fold_w);
         if (rg.keep) {
             sw += wt;
             nk += 1;
@@ -218,7 +219,7 @@ k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom 
     uint32_t kk = 0xFFFFFFFFu;
     if (in) {
         const double wt = (double)wts[m];
-        RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support);
+        RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support, g.fold_w);
         if (rg.keep) {
             const int k = plane_index(rg.w, sc[c].w_lo, sc[c].dw, g.nw);
             const int p0 = (int)rg.cy - g.half;
@@ -420,12 +421,14 @@ k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __re
     const uint32_t kk = key[m];
     if (kk == 0xFFFFFFFFu) return;
     const double wt = (double)wts[m];
-    RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support);
+    RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support, g.fold_w);
     const uint32_t rep = blockIdx.x & (kReplicas - 1);     // the row block's replica (as in k_key)
     const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + rep] + rank[m];
     const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
-    const C v = vis ? vis[m] : cmake<C>((R)0, (R)0);
-    const R w = (R)wts[m];
+    // a prediction's records carry no W*V: their value slot holds (1, 0) for a folded row
+    C v = vis ? vis[m] : cmake<C>(rg.flip ? (R)1 : (R)0, (R)0);
+    if (vis && rg.flip) v.y = -v.y;
+    const R w = vis ? (R)wts[m] : (R)1;
     if (rec_idx) rec_idx[pos] = (uint32_t)m;
     if constexpr (sizeof(R) == 4) {
         const uint32_t ux = frac_code(rg.x - rg.cx), uy = frac_code(rg.y - rg.cy);
@@ -1201,6 +1204,7 @@ __device__ __forceinline__ void degrid_strip(const Geom& g, int c, int k, int s,
                 si += gy * ti;
             }
             const uint32_t m = rec_idx[r];
+            if (v.x != (R)0) si = -si;      // folded row: the transpose of gridding conj(z)
             unsafeAtomicAdd(&vis_out[m].x, sr);
             unsafeAtomicAdd(&vis_out[m].y, si);
         }

@@ -140,7 +140,7 @@ wsimg_status validate_params(const wsimg_params* p, int64_t max_vis) {
     if (!(2.0 * lmax * lmax < 1.0))
         return fail(WSIMG_E_INVALID, "field too wide: a corner pixel has l^2 + m^2 >= 1");
     if (!std::isfinite(p->beta)) return fail(WSIMG_E_INVALID, "beta must be finite");
-    if (p->reserved != 0 || (p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED)) != 0)
+    if (p->reserved != 0 || (p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED | WSIMG_FOLD_W)) != 0)
         return fail(WSIMG_E_INVALID, "unknown flags or reserved field set");
     if (p->flags & WSIMG_FIXED_WRANGE) {
         if (!std::isfinite(p->w_lo) || !std::isfinite(p->w_hi) || p->w_lo > p->w_hi)
@@ -567,6 +567,7 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     g.pixel = p->pixel_rad;
     g.fixed_range = (p->flags & WSIMG_FIXED_WRANGE) ? 1 : 0;
     g.unnormalized = (p->flags & WSIMG_UNNORMALIZED) ? 1 : 0;
+    g.fold_w = (p->flags & WSIMG_FOLD_W) ? 1 : 0;
     g.w_lo_fixed = p->w_lo; g.w_hi_fixed = p->w_hi;
     {
         wsimg_status rs = f32 ? configure<float>(pl) : configure<double>(pl);

@@ -301,3 +301,32 @@ def test_plan_reuse_with_fewer_rows(oracle_mod, c1):
             sub = ds.subset(slice(0, m))
             ref = oracle_mod.wstack_image(sub.uvw_m, sub.vis, sub.weights, sub.freq_hz, _prm(oracle_mod, sub))
             _check(oracle_mod, img, ref, ds.n, ds.support, ds.beta, 1e-5, full=True, tag=f"prefix {m}")
+
+
+# ---------------------------------------------------------------------------------------
+# w-folding (WSIMG_FOLD_W)
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fold_parity_c1(oracle_mod, c1, prec):
+    """Folded imaging against the folded oracle, and against the GPU imaging of rows flipped
+    by hand ((u, v, w, V) -> (-u, -v, -w, conj V) for w < 0) without folding."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision(prec)
+    with ws.Plan(ds.n, ds.pixel_rad, ds.n_wplanes, ds.support, ds.beta, prec, max_vis=ds.m, fold_w=True) as p:
+        img, st = p.image(*_dev(ds, torch), ds.freq_hz, stats=True)
+    img = img.cpu().numpy()
+    prm = _prm(oracle_mod, ds)
+    prm.fold = True
+    pr = oracle_mod.prepare(ds.uvw_m, ds.weights, ds.freq_hz, prm)
+    assert st["w_lo"] == pr.w_lo and st["w_hi"] == pr.w_hi and st["w_lo"] >= 0
+    ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, prm, prepared=pr)
+    _check(oracle_mod, img, ref, ds.n, ds.support, ds.beta, TOL[prec], full=True, tag=f"fold {prec}")
+    neg = ds.uvw_m[:, 2] < 0
+    uvw2 = np.ascontiguousarray(np.where(neg[:, None], -ds.uvw_m, ds.uvw_m))
+    vis2 = np.ascontiguousarray(np.where(neg, np.conj(ds.vis), ds.vis))
+    dev = torch.device("cuda:0")
+    hand = ws.image(torch.from_numpy(uvw2).to(dev), torch.from_numpy(vis2).to(dev),
+                    torch.from_numpy(np.ascontiguousarray(ds.weights)).to(dev), ds.freq_hz, n=ds.n,
+                    pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta).cpu().numpy()
+    assert np.max(np.abs(hand - img)) <= (1e-12 if prec == "f64" else 1e-6) * np.max(np.abs(img))

@@ -449,3 +449,48 @@ def test_predict_point_sources(oracle_mod, c1):
     exact = np.exp(-2j * math.pi * (pr.u * l0 + pr.v * m0 + pr.w * nm1))
     dphi = 2 * math.pi * np.abs(pr.w - wk) * abs(nm1)
     assert np.all(np.abs(y1[pr.keep] - exact[pr.keep]) <= dphi[pr.keep] + 1e-5)
+
+
+# ---------------------------------------------------------------------------------------
+# w-folding (an accuracy variant): rows with w < 0 taken as their conjugate partners
+
+def test_fold_is_the_conjugate_partner(oracle_mod, c1):
+    """P17: folding equals flipping the rows by hand, (u, v, w, V) -> (-u, -v, -w, conj V)
+    for w < 0, and imaging without folding; every kept w is then >= 0; the prediction with
+    folding stays the transpose of the folded imager."""
+    ds = c1.subset(slice(0, 30000))
+    prm_f = _prm(oracle_mod, ds.n, ds.pixel_rad, ds.n_wplanes, ds.support)
+    prm_f.fold = True
+    prm = _prm(oracle_mod, ds.n, ds.pixel_rad, ds.n_wplanes, ds.support)
+    neg = ds.uvw_m[:, 2] < 0
+    assert 0 < neg.sum() < ds.m
+    uvw2 = np.where(neg[:, None], -ds.uvw_m, ds.uvw_m)
+    vis2 = np.where(neg, np.conj(ds.vis), ds.vis)
+    Df = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, prm_f)
+    Dh = oracle_mod.wstack_image(uvw2, vis2, ds.weights, ds.freq_hz, prm)
+    assert np.max(np.abs(Df - Dh)) <= 1e-13 * np.max(np.abs(Dh))
+    pr = oracle_mod.prepare(ds.uvw_m, ds.weights, ds.freq_hz, prm_f)
+    assert pr.w_lo >= 0 and np.all(pr.w[pr.keep] >= 0)
+    rng = np.random.default_rng(51)
+    z = rng.normal(size=ds.m) + 1j * rng.normal(size=ds.m)
+    X = rng.normal(size=(ds.n, ds.n))
+    ones = np.ones(ds.m)
+    A = oracle_mod.wstack_image(ds.uvw_m, z, ones, ds.freq_hz, prm_f, normalize=False)
+    y = oracle_mod.wstack_predict(ds.uvw_m, ones, ds.freq_hz, prm_f, X)
+    lhs, rhs = float(np.sum(A * X)), float(np.real(np.sum(z * np.conj(y))))
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+def test_fold_reduces_the_w_error(oracle_mod, c1):
+    """P18: at the same number of planes, folding halves the w range per plane, so the
+    w-stacked image moves closer to the direct DFT of Eq. 1 (inner half of the image)."""
+    ds = c1
+    Dd = oracle_mod.dft_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, ds.n, ds.pixel_rad)
+    c = slice(ds.n // 4, 3 * ds.n // 4)
+    errs = []
+    for fold in (False, True):
+        prm = _prm(oracle_mod, ds.n, ds.pixel_rad, ds.n_wplanes, ds.support)
+        prm.fold = fold
+        D = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, prm)
+        errs.append(np.linalg.norm((D - Dd)[c, c]) / np.linalg.norm(Dd[c, c]))
+    assert errs[1] < 0.7 * errs[0], errs
