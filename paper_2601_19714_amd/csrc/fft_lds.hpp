@@ -81,6 +81,36 @@ template <int RAD, typename C> __device__ __forceinline__ void dft_small(C* x) {
     else dft16(x);
 }
 
+// x[m] *= tw[(m k) << TWSHIFT] for m = 1 .. RAD-1.  With WSIMG_TW_DERIVE = 1 a
+// radix-8 (radix-4) pass reads the powers m = 1, 2, 4 (1, 2) from the table and forms the
+// others as their products (one extra rounding each), so fewer twiddles stay live in
+// registers when a kernel keeps them across its loop.
+#ifndef WSIMG_TW_DERIVE
+#define WSIMG_TW_DERIVE 0
+#endif
+template <int RAD, int TWSHIFT, typename C>
+__device__ __forceinline__ void twiddle_inputs(C* x, const C* __restrict__ tw, int k) {
+    if constexpr (WSIMG_TW_DERIVE && RAD == 8) {
+        const C w1 = tw[k << TWSHIFT], w2 = tw[(2 * k) << TWSHIFT], w4 = tw[(4 * k) << TWSHIFT];
+        const C w3 = cmul(w1, w2);
+        x[1] = cmul(x[1], w1);
+        x[2] = cmul(x[2], w2);
+        x[3] = cmul(x[3], w3);
+        x[4] = cmul(x[4], w4);
+        x[5] = cmul(x[5], cmul(w1, w4));
+        x[6] = cmul(x[6], cmul(w2, w4));
+        x[7] = cmul(x[7], cmul(w3, w4));
+    } else if constexpr (WSIMG_TW_DERIVE && RAD == 4) {
+        const C w1 = tw[k << TWSHIFT], w2 = tw[(2 * k) << TWSHIFT];
+        x[1] = cmul(x[1], w1);
+        x[2] = cmul(x[2], w2);
+        x[3] = cmul(x[3], cmul(w1, w2));
+    } else {
+#pragma unroll
+        for (int m = 1; m < RAD; ++m) x[m] = cmul(x[m], tw[(m * k) << TWSHIFT]);
+    }
+}
+
 template <int V> struct Log2Of {
     static constexpr int value = V == 2 ? 1 : V == 4 ? 2 : V == 8 ? 3 : 4;          // radices
     static constexpr int value_any = V <= 1 ? 0 : 1 + Log2Of<(V > 1 ? V / 2 : 1)>::value_any;
@@ -126,10 +156,7 @@ __device__ __forceinline__ void stockham_pass(C* lds, const C* __restrict__ tw) 
         if (NBF % NT == 0 || g < NBF) {
             const int r = g >> LSUB, b = g & ((1 << LSUB) - 1);
             const int k = b & (L - 1), j = b >> LOG2L;
-            if constexpr (L > 1) {
-#pragma unroll
-                for (int m = 1; m < RAD; ++m) x[t][m] = cmul(x[t][m], tw[(m * k) << TWSHIFT]);
-            }
+            if constexpr (L > 1) twiddle_inputs<RAD, TWSHIFT>(x[t], tw, k);
             dft_small<RAD>(x[t]);
             const int obase = (r << LOG2N) + (j << (LOG2L + LOGR)) + k;
 #pragma unroll
@@ -179,8 +206,7 @@ __device__ __forceinline__ void fft_last_to_regs(const C* lds, const C* __restri
             const int base = (r << LOG2N) + b;
 #pragma unroll
             for (int m = 0; m < RAD; ++m) x[m] = lds[lds_pad(base + (m << LSUB))];
-#pragma unroll
-            for (int m = 1; m < RAD; ++m) x[m] = cmul(x[m], tw[m * b]);
+            twiddle_inputs<RAD, 0>(x, tw, b);
             dft_small<RAD>(x);
         } else {
 #pragma unroll
