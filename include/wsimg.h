@@ -64,6 +64,13 @@ typedef enum {
 #define WSIMG_UNNORMALIZED 0x2u   /* wsimg_image does not divide by the sum of weights:
                                      the image is then A(W V), the imaging operator that
                                      wsimg_predict is the transpose of                    */
+#define WSIMG_PAD2 0x8u           /* a grid of twice the image side (n <= 4096): the image is
+                                     the central n x n of the transformed 2n x 2n grid, the
+                                     cell size is 1/(2 n pixel_rad) and the taper is taken
+                                     at xi = (j - n/2) / (2n), so the edge amplification of
+                                     the taper division drops from C(0)^2/C(1/2)^2 to
+                                     C(0)^2/C(1/4)^2 (about 6 for W = 7).  wsimg_grid then
+                                     writes [n_wplanes][2n][2n]                          */
 #define WSIMG_FOLD_W 0x4u         /* w-folding: a row with w < 0 is taken as its conjugate
                                      partner (-u, -v, -w, conj V) (equal for a real sky),
                                      so the planes span |w| only; the real image is the same
@@ -101,6 +108,7 @@ typedef struct {
     int64_t max_vis;
     int64_t device_bytes;    /* device memory the plan holds                               */
     int64_t max_channels;    /* channels one wsimg_image_batch call may image              */
+    int64_t n_grid;          /* grid side: n, or 2n with WSIMG_PAD2                        */
 } wsimg_plan_info;
 
 #define WSIMG_N_KERNELS 8

@@ -48,6 +48,16 @@ class Params:
     w_lo: Optional[float] = None    # both None: the range comes from the data
     w_hi: Optional[float] = None
     fold: bool = False              # w-folding: a row with w < 0 is imaged as its conjugate partner
+    pad: int = 1                    # grid side = pad * n; the image is the grid image's central n x n
+
+    @property
+    def n_grid(self) -> int:
+        return self.pad * self.n
+
+    @property
+    def crop(self) -> int:
+        """Offset of the image inside the transformed grid, (n_grid - n) / 2."""
+        return (self.n_grid - self.n) // 2
 
 
 @dataclasses.dataclass
@@ -77,7 +87,7 @@ def prepare(uvw_m: np.ndarray, weights: np.ndarray, freq_hz: float, prm: Params)
     """Steps 1-3: wavelength coordinates, tap origins, the keep mask and plane indices."""
     uvw_m = np.asarray(uvw_m, dtype=np.float64)
     wt = np.asarray(weights).astype(np.float64)
-    n, W = prm.n, prm.support
+    n, W = prm.n_grid, prm.support
     u = uvw_m[:, 0] * freq_hz / C_LIGHT
     v = uvw_m[:, 1] * freq_hz / C_LIGHT
     w = uvw_m[:, 2] * freq_hz / C_LIGHT
@@ -131,7 +141,7 @@ def tap_weights(pr: Prepared, prm: Params, rows: np.ndarray) -> Tuple[np.ndarray
 def grid_plane(pr: Prepared, vis: np.ndarray, weights: np.ndarray, prm: Params, plane: int,
                chunk: int = 1 << 20) -> np.ndarray:
     """Step 5 for one w-plane: the complex float64 grid [N, N] of Eq. 3."""
-    n = prm.n
+    n = prm.n_grid
     grid = np.zeros((n, n, 2), dtype=np.float64)
     rows = np.nonzero(pr.keep & (pr.k == plane))[0]
     vis = np.asarray(vis)
@@ -224,19 +234,20 @@ def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
         if not np.any(pr.keep & (pr.k == k)):
             continue
         g = grid_plane(pr, vis, weights, prm, k)
+        o = prm.crop
         if pixels is None:
-            P = plane_transform(g)
+            P = plane_transform(g)[o:o + n, o:o + n]
         else:
             sel = pr.keep & (pr.k == k)
             lo, hi = int(pr.p0[sel].min()), int(pr.p0[sel].max()) + prm.support - 1
-            P = plane_transform(g, (rows, cols), grid_rows=np.arange(lo, hi + 1))
+            P = plane_transform(g, (rows + o, cols + o), grid_rows=np.arange(lo, hi + 1))
         del g
         wk = pr.w_lo + (k + 0.5) * pr.dw
         cyc = wk * nm1
         cyc = cyc - np.round(cyc)
         S += P * np.exp(2j * math.pi * cyc)
-    xi_j = (cols - n // 2) / n
-    xi_i = (rows - n // 2) / n
+    xi_j = (cols - n // 2) / prm.n_grid
+    xi_i = (rows - n // 2) / prm.n_grid
     corr = np.outer(_kb.kb_taper(xi_i, prm.support, prm.beta), _kb.kb_taper(xi_j, prm.support, prm.beta))
     D = S / ((pr.sum_w if normalize else 1.0) * corr)
     return D if complex_out else D.real
@@ -244,7 +255,7 @@ def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
 
 def grid_stack(uvw_m, vis, weights, freq_hz: float, prm: Params,
                prepared: Optional[Prepared] = None) -> np.ndarray:
-    """Step 5 for every plane: the complex float64 grid [Nw, N, N]."""
+    """Step 5 for every plane: the complex float64 grid [Nw, pad N, pad N]."""
     pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
     return np.stack([grid_plane(pr, vis, weights, prm, k) for k in range(prm.n_wplanes)])
 
@@ -266,11 +277,11 @@ def wstack_predict(uvw_m, weights, freq_hz: float, prm: Params, image: np.ndarra
     Dropped rows predict 0.  ``weights`` only decide which rows are kept and the plane range
     (as in steps 2-3); they do not scale the prediction.
     """
-    n = prm.n
+    n, ng, o = prm.n, prm.n_grid, prm.crop
     pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
     rows = cols = np.arange(n)
     _, _, nm1 = direction_cosines(n, prm.pixel_rad, rows, cols)
-    xi = (rows - n // 2) / n
+    xi = (rows - n // 2) / ng
     ck = _kb.kb_taper(xi, prm.support, prm.beta)
     Y = np.asarray(image, dtype=np.float64) / np.outer(ck, ck)
     out = np.zeros(pr.u.shape[0], dtype=np.complex128)
@@ -282,13 +293,15 @@ def wstack_predict(uvw_m, weights, freq_hz: float, prm: Params, image: np.ndarra
         wk = pr.w_lo + (k + 0.5) * pr.dw
         cyc = wk * nm1
         cyc = cyc - np.round(cyc)
-        g = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(Y * np.exp(-2j * math.pi * cyc))))
+        Yk = np.zeros((ng, ng), dtype=np.complex128)
+        Yk[o:o + n, o:o + n] = Y * np.exp(-2j * math.pi * cyc)     # the image inside the grid image
+        g = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(Yk)))
         gri = np.ascontiguousarray(np.stack([g.real, g.imag], axis=-1))
         gx, gy = tap_weights(pr, prm, sel)
         p0 = np.ascontiguousarray(pr.p0[sel])
         q0 = np.ascontiguousarray(pr.q0[sel])
         res = np.zeros((sel.size, 2), dtype=np.float64)
-        L.oracle_degrid(n, prm.support, sel.size, _ptr(p0), _ptr(q0), _ptr(gx), _ptr(gy), _ptr(gri),
+        L.oracle_degrid(ng, prm.support, sel.size, _ptr(p0), _ptr(q0), _ptr(gx), _ptr(gy), _ptr(gri),
                         _ptr(res))
         out[sel] = res[:, 0] + 1j * res[:, 1]
     if pr.flip is not None:

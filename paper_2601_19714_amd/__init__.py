@@ -53,7 +53,7 @@ class Plan:
     def __init__(self, n: int, pixel_rad: float, n_wplanes: int, support: int = 7,
                  beta: Optional[float] = None, precision: str = "f32", max_vis: int = 0,
                  w_range: Optional[Tuple[float, float]] = None, device=None, max_channels: int = 1,
-                 normalize: bool = True, fold_w: bool = False):
+                 normalize: bool = True, fold_w: bool = False, pad: int = 1):
         import torch
 
         self._torch = torch
@@ -74,6 +74,11 @@ class Plan:
             p.flags |= _lib.WSIMG_UNNORMALIZED
         if fold_w:
             p.flags |= _lib.WSIMG_FOLD_W
+        if pad not in (1, 2):
+            raise ValueError("pad must be 1 or 2")
+        if pad == 2:
+            p.flags |= _lib.WSIMG_PAD2
+        self.pad = int(pad)
         self._L = _lib.load()
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -195,7 +200,8 @@ class Plan:
     def grid(self, uvw, vis, weights, freq_hz: float, out=None, stats: bool = False):
         """The gridding step alone: complex grid [n_wplanes, n, n] (wsimg_grid)."""
         cdt, _ = self._dtypes()
-        shape = (self.n_wplanes, self.n, self.n)
+        ng = self.pad * self.n
+        shape = (self.n_wplanes, ng, ng)
         if out is None:
             out = self._torch.empty(shape, dtype=cdt, device=self.device)
         elif out.dtype != cdt or tuple(out.shape) != shape or not out.is_contiguous() or out.device != self.device:

@@ -20,6 +20,7 @@ WSIMG_F64 = 2
 WSIMG_FIXED_WRANGE = 0x1
 WSIMG_UNNORMALIZED = 0x2
 WSIMG_FOLD_W = 0x4
+WSIMG_PAD2 = 0x8
 WSIMG_N_KERNELS = 8
 
 # every symbol include/wsimg.h declares
@@ -47,7 +48,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("strip_rows", ctypes.c_int32), ("col_block", ctypes.c_int32),
                 ("n_buckets", ctypes.c_int64), ("max_vis", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("max_channels", ctypes.c_int64)]
+                ("max_channels", ctypes.c_int64), ("n_grid", ctypes.c_int64)]
 
 
 class Timing(ctypes.Structure):

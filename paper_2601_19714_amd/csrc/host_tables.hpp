@@ -84,9 +84,11 @@ inline std::vector<ld> kb_tap_polynomials(int W, ld beta, int deg) {
     return out;
 }
 
-inline std::vector<ld> inverse_taper(int n, int W, ld beta) {
+// 1 / C(xi) for image pixels i = 0 .. n-1, xi = (i - n/2) / n_grid (n_grid = n, or 2n for a
+// padded grid).
+inline std::vector<ld> inverse_taper(int n, int n_grid, int W, ld beta) {
     std::vector<ld> out(n);
-    for (int i = 0; i < n; ++i) out[i] = 1.0L / kb_transform((ld)(i - n / 2) / (ld)n, W, beta);
+    for (int i = 0; i < n; ++i) out[i] = 1.0L / kb_transform((ld)(i - n / 2) / (ld)n_grid, W, beta);
     return out;
 }
 

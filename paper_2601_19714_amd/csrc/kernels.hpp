@@ -31,8 +31,12 @@
 namespace wsimg {
 
 // Plan constants handed to every kernel by value.
+// n is the grid side: the image side n_img times the padding (1 or 2); the image is the grid
+// image's central n_img x n_img, starting at row and column crop = (n - n_img) / 2.
 struct Geom {
     int n, log2n, nw, support, half;
+    int n_img, crop;
+    size_t plane_elems;     // elements of one plane of the intermediate: n * n_img
     int H, log2H, S;        // grid rows per strip, strips per plane
     int nb1;                // buckets per channel: nw * S
     int B, log2B, NB;       // image columns per stacking block, blocks
@@ -619,7 +623,7 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
     static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);
     static constexpr int PX2 = sizeof(R) == 4 ? WSIMG_F32_PX2 : WSIMG_F64_PX2;
-    static constexpr int B0 = PX2 / N < N ? PX2 / N : N;
+    static constexpr int B0 = PX2 / N < N / 2 ? PX2 / N : N / 2;   // at most half a (padded) grid
     static constexpr int B = B0 < 1 ? 1 : B0;
     static constexpr int NT2 = (B * N / E2) < 64 ? 64 : (B * N / E2);
     static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
@@ -796,15 +800,17 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
         fft_rows_lds<LOG2N, SH::LR1, H, NT>(lds, tw);
         // column-block layout [k][jb][p'][B], p' = (p + n/2) mod n: the next pass reads a
         // contiguous [n][B] block per plane.  Image column j takes FFT bin (j + n/2) mod n.
+        // only the image's columns are kept (the crop of a padded grid)
         constexpr int B = SH::B, LOG2B = Log2Of<B>::value_any;
         const int pp0 = (row0 + (n >> 1)) & nmask;
-        C* dst = out + ((size_t)(c * g.nw + k) << (2 * LOG2N));
+        C* dst = out + (size_t)(c * g.nw + k) * g.plane_elems;
         constexpr int LHB = LOG2H + LOG2B;
-        for (int e = tid; e < elems; e += NT) {
+        const int out_elems = H * g.n_img;
+        for (int e = tid; e < out_elems; e += NT) {
             const int jb = e >> LHB;
             const int rem = e & ((1 << LHB) - 1);
             const int lr = rem >> LOG2B, col = rem & (B - 1);
-            const int jp = (((jb << LOG2B) + col) + (n >> 1)) & nmask;
+            const int jp = (g.crop + (jb << LOG2B) + col + (n >> 1)) & nmask;
             dst[(((size_t)jb << LOG2N) + pp0 + lr) * B + col] = lds[lds_pad((lr << LOG2N) + jp)];
         }
     } else {
@@ -909,7 +915,8 @@ __device__ __forceinline__ void pass2_load(const typename Cx<R>::T* __restrict__
 #define WSIMG_COLS_WAVES_PER_EU 0
 #endif
 
-template <typename R, int LOG2N>
+// PAD: the grid is padded (the image is its central crop); without it the crop logic folds away.
+template <typename R, int LOG2N, bool PAD>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT2), WSIMG_COLS_WAVES_PER_EU)
 k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ occ,
              const uint8_t* __restrict__ plane_occ, const typename Cx<R>::T* __restrict__ inter,
@@ -930,11 +937,13 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     double nm1r[SH::NM1_LDS ? 1 : E];
     nm1r[0] = 0.0;
     const int jb = blockIdx.x, c = blockIdx.y;
+    const int crop = PAD ? g.crop : 0, nimg = PAD ? g.n_img : n;
     const int tid = threadIdx.x;
     const bool first_active = tid < (elems >> LR);
     const uint8_t* pocc = plane_occ + (size_t)c * g.nw;
     const uint8_t* socc = occ + (size_t)c * g.nb1;
-    const typename Cx<R>::T* cin = inter + ((size_t)c * g.nw << (2 * LOG2N));
+    const size_t plane_elems = PAD ? g.plane_elems : ((size_t)1 << (2 * LOG2N));
+    const typename Cx<R>::T* cin = inter + (size_t)c * g.nw * plane_elems;
 
     // comp is the Kahan compensation (float only)
     R acc[E], comp[sizeof(R) == 4 ? E : 1];
@@ -946,10 +955,12 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         int col, ip;
         double v = 0.0;
         if (last_slot<LOG2N, LR, B, NT>(tid, s, col, ip)) {
-            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
-            const double l = (double)(j - hn) * g.pixel, m = (double)(i - hn) * g.pixel;
-            const double r2 = m * m + l * l;
-            v = -r2 / (1.0 + sqrt(1.0 - r2));
+            const int i = ((ip + hn) & nmask) - crop, j = (jb << LOG2B) + col;   // image pixel
+            if (!PAD || (i >= 0 && i < nimg)) {
+                const double l = (double)(j - (nimg >> 1)) * g.pixel, m = (double)(i - (nimg >> 1)) * g.pixel;
+                const double r2 = m * m + l * l;
+                v = -r2 / (1.0 + sqrt(1.0 - r2));
+            }
         }
         if constexpr (SH::NM1_LDS) nm1s[s * NT + tid] = v;
         else nm1r[s] = v;
@@ -960,7 +971,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     while (k < g.nw && !pocc[k]) ++k;
     C x[E], pf[E];
     if (k < g.nw)
-        pass2_load<R, LOG2N, LR, B>(cin + ((size_t)k << (2 * LOG2N)) + (size_t)jb * elems,
+        pass2_load<R, LOG2N, LR, B>(cin + (size_t)k * plane_elems + (size_t)jb * elems,
                                 socc + (size_t)k * g.S, tid, first_active, g.log2H, pf);
     while (k < g.nw) {
         int kn = k + 1;
@@ -969,7 +980,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         for (int m = 0; m < E; ++m) x[m] = pf[m];
         if constexpr (Pass2Prefetch<R>::value) {
             if (kn < g.nw)
-                pass2_load<R, LOG2N, LR, B>(cin + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
+                pass2_load<R, LOG2N, LR, B>(cin + (size_t)kn * plane_elems + (size_t)jb * elems,
                                         socc + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
         }
         // first pass: radix E with L = 1 (no twiddles), registers to LDS
@@ -1014,7 +1025,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         }
         if constexpr (!Pass2Prefetch<R>::value) {
             if (kn < g.nw)
-                pass2_load<R, LOG2N, LR, B>(cin + ((size_t)kn << (2 * LOG2N)) + (size_t)jb * elems,
+                pass2_load<R, LOG2N, LR, B>(cin + (size_t)kn * plane_elems + (size_t)jb * elems,
                                         socc + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
         }
         __syncthreads();
@@ -1027,9 +1038,10 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     for (int s = 0; s < E; ++s) {
         int col, ip;
         if (last_slot<LOG2N, LR, B, NT>(tid, s, col, ip)) {
-            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
-            image[((size_t)c << (2 * LOG2N)) + (size_t)i * n + j] =
-                scale_ok ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
+            const int i = ((ip + hn) & nmask) - crop, j = (jb << LOG2B) + col;
+            if (!PAD || (i >= 0 && i < nimg))
+                image[(size_t)c * nimg * nimg + (size_t)i * nimg + j] =
+                    scale_ok ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
         }
     }
 }
@@ -1068,7 +1080,7 @@ k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ o
     const int tid = threadIdx.x;
     const uint8_t* pocc = plane_occ + (size_t)c * g.nw;
     const uint8_t* socc = occ + (size_t)c * g.nb1;
-    const R* img = image + ((size_t)c << (2 * LOG2N));
+    const R* img = image + (size_t)c * g.n_img * g.n_img;
 
     // this thread's pixels e = tid + t * NT (column (e >> LOG2N) of the block, bin e mod N)
     R xt[PER];
@@ -1080,11 +1092,13 @@ k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ o
         nm1[t] = 0.0;
         if (PER * NT == elems || e < elems) {
             const int col = e >> LOG2N, ip = e & nmask;
-            const int i = (ip + hn) & nmask, j = (jb << LOG2B) + col;
-            xt[t] = img[(size_t)i * n + j] * inv_taper[i] * inv_taper[j];
-            const double l = (double)(j - hn) * g.pixel, m = (double)(i - hn) * g.pixel;
-            const double r2 = m * m + l * l;
-            nm1[t] = -r2 / (1.0 + sqrt(1.0 - r2));
+            const int i = ((ip + hn) & nmask) - g.crop, j = (jb << LOG2B) + col;   // image pixel
+            if (i >= 0 && i < g.n_img) {       // outside the image (a padded grid): zero
+                xt[t] = img[(size_t)i * g.n_img + j] * inv_taper[i] * inv_taper[j];
+                const double l = (double)(j - (g.n_img >> 1)) * g.pixel, m = (double)(i - (g.n_img >> 1)) * g.pixel;
+                const double r2 = m * m + l * l;
+                nm1[t] = -r2 / (1.0 + sqrt(1.0 - r2));
+            }
         }
     }
     const double w_lo = sc[c].w_lo, dw = sc[c].dw;
@@ -1115,7 +1129,7 @@ k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ o
         }
         __syncthreads();
         fft_rows_lds<LOG2N, LR, B, NT>(lds, tw);
-        C* dst = inter + ((size_t)(c * g.nw + k) << (2 * LOG2N)) + (size_t)jb * elems;
+        C* dst = inter + (size_t)(c * g.nw + k) * g.plane_elems + (size_t)jb * elems;
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
             const int f = tid + t * NT;       // [p'][col] order: contiguous in the intermediate
@@ -1156,11 +1170,16 @@ __device__ __forceinline__ void degrid_strip(const Geom& g, int c, int k, int s,
     const int tid = threadIdx.x;
     const int row0 = s * H;
     const int pp0 = (row0 + hn) & nmask;        // a strip never wraps in p' (H divides N/2)
-    const C* src = inter + ((size_t)(c * g.nw + k) << (2 * LOG2N));
-    for (int e = tid; e < elems; e += NT) {
+    const C* src = inter + (size_t)(c * g.nw + k) * g.plane_elems;
+    if (g.crop > 0) {      // a padded grid: the columns outside the image are zero
+        for (int e = tid; e < elems; e += NT) lds[lds_pad(e)] = cmake<C>((R)0, (R)0);
+        __syncthreads();
+    }
+    const int in_elems = H * g.n_img;
+    for (int e = tid; e < in_elems; e += NT) {
         const int jb = e >> LHB, rem = e & ((1 << LHB) - 1);
         const int lr = rem >> LOG2B, col = rem & (B - 1);
-        const int j = (jb << LOG2B) + col;
+        const int j = g.crop + (jb << LOG2B) + col;
         const C v = src[((size_t)jb << LOG2N) * B + (size_t)(pp0 + lr) * B + col];
         lds[lds_pad((lr << LOG2N) + ((j + hn) & nmask))] = cmake<C>(v.x, -v.y);
     }

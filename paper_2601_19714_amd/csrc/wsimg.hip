@@ -140,8 +140,11 @@ wsimg_status validate_params(const wsimg_params* p, int64_t max_vis) {
     if (!(2.0 * lmax * lmax < 1.0))
         return fail(WSIMG_E_INVALID, "field too wide: a corner pixel has l^2 + m^2 >= 1");
     if (!std::isfinite(p->beta)) return fail(WSIMG_E_INVALID, "beta must be finite");
-    if (p->reserved != 0 || (p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED | WSIMG_FOLD_W)) != 0)
+    if (p->reserved != 0 ||
+        (p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED | WSIMG_FOLD_W | WSIMG_PAD2)) != 0)
         return fail(WSIMG_E_INVALID, "unknown flags or reserved field set");
+    if ((p->flags & WSIMG_PAD2) && p->n > 4096)
+        return fail(WSIMG_E_UNSUPPORTED, "a padded grid is at most 8192 cells: n <= 4096 with WSIMG_PAD2");
     if (p->flags & WSIMG_FIXED_WRANGE) {
         if (!std::isfinite(p->w_lo) || !std::isfinite(p->w_hi) || p->w_lo > p->w_hi)
             return fail(WSIMG_E_INVALID, "fixed w range must be finite with w_lo <= w_hi");
@@ -154,15 +157,15 @@ wsimg_status validate_params(const wsimg_params* p, int64_t max_vis) {
 template <typename R>
 wsimg_status upload_tables(wsimg_plan* pl) {
     using C = typename Cx<R>::T;
-    const int n = pl->p.n, W = pl->p.support;
+    const int n = pl->g.n, n_img = pl->g.n_img, W = pl->p.support;
     const host::ld beta = (host::ld)pl->p.beta;
     const int deg = KbDeg<R>::value;
     std::vector<host::ld> coef = host::kb_tap_polynomials(W, beta, deg);
     std::vector<R> hc(coef.size());
     for (size_t i = 0; i < coef.size(); ++i) hc[i] = (R)coef[i];
-    std::vector<host::ld> taper = host::inverse_taper(n, W, beta);
-    std::vector<R> ht(n);
-    for (int i = 0; i < n; ++i) ht[i] = (R)taper[i];
+    std::vector<host::ld> taper = host::inverse_taper(n_img, n, W, beta);
+    std::vector<R> ht(n_img);
+    for (int i = 0; i < n_img; ++i) ht[i] = (R)taper[i];
     std::vector<host::ld> tre, tim;
     host::twiddles(n, tre, tim);
     std::vector<C> htw(n);
@@ -192,7 +195,9 @@ wsimg_status configure_shape(wsimg_plan* pl) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_only<R, LOG2N, kMaxSupport>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
-    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N>,
+    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
+    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
     WS_HIP(hipFuncSetAttribute((const void*)k_adj_cols<R, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
@@ -238,10 +243,14 @@ template <typename R, int LOG2N>
 wsimg_status launch_cols(wsimg_plan* pl, int nch, void* image) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
-    hipLaunchKernelGGL((k_cols_stack<R, LOG2N>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2), pl->lds2,
-                       pl->stream, g,
-                       pl->scalars, pl->occ, pl->plane_occ, (const C*)pl->inter, (const C*)pl->tw,
-                       (const R*)pl->inv_taper, (R*)image);
+    if (g.crop > 0)
+        hipLaunchKernelGGL((k_cols_stack<R, LOG2N, true>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2),
+                           pl->lds2, pl->stream, g, pl->scalars, pl->occ, pl->plane_occ, (const C*)pl->inter,
+                           (const C*)pl->tw, (const R*)pl->inv_taper, (R*)image);
+    else
+        hipLaunchKernelGGL((k_cols_stack<R, LOG2N, false>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2),
+                           pl->lds2, pl->stream, g, pl->scalars, pl->occ, pl->plane_occ, (const C*)pl->inter,
+                           (const C*)pl->tw, (const R*)pl->inv_taper, (R*)image);
     WS_LAUNCH_CHECK("cols_stack");
     return WSIMG_OK;
 }
@@ -559,9 +568,13 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     const bool f32 = p->precision == WSIMG_F32;
     pl->rbytes = f32 ? 4 : 8;
     pl->cbytes = 2 * pl->rbytes;
-    const int n = p->n;
+    const int n_img = p->n;
+    const int n = (p->flags & WSIMG_PAD2) ? 2 * n_img : n_img;      // grid side
     Geom& g = pl->g;
     g.n = n; g.log2n = ilog2(n); g.nw = p->n_wplanes; g.support = p->support; g.half = (p->support - 1) / 2;
+    g.n_img = n_img;
+    g.crop = (n - n_img) / 2;
+    g.plane_elems = (size_t)n * (size_t)n_img;
     g.du = 1.0 / ((double)n * p->pixel_rad);
     g.half_n = (double)n / 2.0;
     g.pixel = p->pixel_rad;
@@ -575,6 +588,7 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     }
     pl->nb = (int64_t)g.nw * g.S;
     g.nb1 = (int)pl->nb;
+    g.NB = n_img / g.B;             // stacking blocks cover the image's columns only
     if (pl->nb * max_channels > kMaxBucketsTotal) {
         delete pl;
         return fail(WSIMG_E_UNSUPPORTED, "max_channels x n_wplanes x strips exceeds 2^25 sort buckets");
@@ -591,7 +605,7 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     wsimg_status r = WSIMG_OK;
     const size_t mv = (size_t)std::max<int64_t>(max_vis, 1);
     const size_t mc = (size_t)max_channels;
-    const size_t cells = (size_t)g.nw * (size_t)n * (size_t)n;
+    const size_t cells = (size_t)g.nw * g.plane_elems;
     const size_t nbt = (size_t)pl->nb * mc;
     size_t nparts_alloc = 0;
     for (int c = 1; c <= max_channels; ++c) nparts_alloc = std::max(nparts_alloc, (size_t)c * parts_target(c));
@@ -618,7 +632,7 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     ALLOC(rec2, (f32 ? 16 : 32) * mv, "records by origin");
     ALLOC(inter, pl->cbytes * cells * mc, "row-transformed planes");
     ALLOC(tw, pl->cbytes * n, "twiddles");
-    ALLOC(inv_taper, pl->rbytes * n, "taper");
+    ALLOC(inv_taper, pl->rbytes * n_img, "taper");
     ALLOC(kbc, pl->rbytes * (size_t)p->support * 17, "kernel polynomials");
 #undef ALLOC
     if (!r) {
@@ -701,6 +715,7 @@ wsimg_status wsimg_plan_get_info(const wsimg_plan* plan, wsimg_plan_info* info) 
     info->max_vis = plan->max_vis;
     info->device_bytes = plan->device_bytes;
     info->max_channels = plan->max_channels;
+    info->n_grid = plan->g.n;
     return WSIMG_OK;
 }
 

@@ -196,3 +196,34 @@ def test_predict_fold(oracle_mod, c1, prec):
     rhs = float(np.real(np.sum(z.astype(np.complex128) * np.conj(y))))
     scale = float(np.linalg.norm(Az) * np.linalg.norm(X))
     assert abs(lhs - rhs) <= (1e-12 if prec == "f64" else 1e-5) * scale
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_predict_pad2(oracle_mod, c1, prec):
+    """Prediction on a padded grid against the padded oracle prediction, with the
+    dot-product identity against the padded imager on the GPU."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision(prec)
+    rng = np.random.default_rng(67)
+    rdt = np.float32 if prec == "f32" else np.float64
+    cdt = np.complex64 if prec == "f32" else np.complex128
+    X = rng.normal(size=(ds.n, ds.n)).astype(rdt)
+    z = (rng.normal(size=ds.m) + 1j * rng.normal(size=ds.m)).astype(cdt)
+    ones = np.ones(ds.m, dtype=rdt)
+    uvw, w1 = _t(torch, ds.uvw_m), _t(torch, ones)
+    kw = dict(support=ds.support, beta=ds.beta, precision=prec, max_vis=ds.m, pad=2)
+    with ws.Plan(ds.n, ds.pixel_rad, ds.n_wplanes, **kw) as p:
+        y = p.predict(uvw, w1, ds.freq_hz, _t(torch, X)).cpu().numpy().astype(np.complex128)
+    with ws.Plan(ds.n, ds.pixel_rad, ds.n_wplanes, normalize=False, **kw) as p:
+        Az = p.image(uvw, _t(torch, z), w1, ds.freq_hz).cpu().numpy().astype(np.float64)
+    d64 = c1.as_precision("f64")
+    prm = _prm(oracle_mod, d64)
+    prm.pad = 2
+    ref = oracle_mod.wstack_predict(d64.uvw_m, np.ones(ds.m), d64.freq_hz, prm, X.astype(np.float64))
+    err = _rel(y, ref)
+    print(f"predict pad2 {prec}: rel L2 {err:.3e}")
+    assert err <= (1e-12 if prec == "f64" else 1e-5)
+    lhs = float(np.sum(Az * X.astype(np.float64)))
+    rhs = float(np.real(np.sum(z.astype(np.complex128) * np.conj(y))))
+    assert abs(lhs - rhs) <= (1e-12 if prec == "f64" else 1e-5) * float(np.linalg.norm(Az) * np.linalg.norm(X))

@@ -330,3 +330,41 @@ def test_fold_parity_c1(oracle_mod, c1, prec):
                     torch.from_numpy(np.ascontiguousarray(ds.weights)).to(dev), ds.freq_hz, n=ds.n,
                     pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta).cpu().numpy()
     assert np.max(np.abs(hand - img)) <= (1e-12 if prec == "f64" else 1e-6) * np.max(np.abs(img))
+
+
+# ---------------------------------------------------------------------------------------
+# grid padding x2 (WSIMG_PAD2)
+
+def _taper_pad(oracle, n, W, beta):
+    xi = (np.arange(n) - n // 2) / (2 * n)
+    return oracle.kb.kb_taper(xi, W, beta) / oracle.kb.kb_taper(0.0, W, beta)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,nw,W,m", [(16, 1, 3, 40), (64, 3, 15, 3000), (256, 7, 9, 30000), (1024, 3, 7, 100000)])
+def test_pad2_parity(oracle_mod, prec, n, nw, W, m):
+    """Padded imaging (2n grid, central crop) against the padded oracle: untapered image
+    everywhere and the image itself everywhere (the taper's edge amplification is at most
+    C(0)^2/C(1/4)^2: 5.9 for W = 7, 52 for W = 15), and the padded grid [nw][2n][2n]."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = _random_ds(700 + n + W, m, n, nw, W, prec)
+    with ws.Plan(n, ds.pixel_rad, nw, W, ds.beta, prec, max_vis=ds.m, pad=2) as p:
+        assert p.info()["n_grid"] == 2 * n
+        img = p.image(*_dev(ds, torch), ds.freq_hz).cpu().numpy()
+        grd = p.grid(*_dev(ds, torch), ds.freq_hz).cpu().numpy()
+    d64 = ds.as_precision("f64")
+    prm = _prm(oracle_mod, d64)
+    prm.pad = 2
+    ref = oracle_mod.wstack_image(d64.uvw_m, d64.vis, d64.weights, d64.freq_hz, prm)
+    t = _taper_pad(oracle_mod, n, W, ds.beta)
+    tt = np.outer(t, t)
+    ua = _errs(img * tt, ref * tt)
+    fa = _errs(img, ref)
+    print(f"pad2 n={n} W={W} {prec}: untapered {ua[0]:.2e}/{ua[1]:.2e} full {fa[0]:.2e}/{fa[1]:.2e}")
+    tol = TOL[prec]
+    assert ua[0] <= tol and ua[1] <= tol
+    assert fa[0] <= tol and fa[1] <= (tol if W <= 9 else 10 * tol)
+    gref = oracle_mod.grid_stack(d64.uvw_m, d64.vis, d64.weights, d64.freq_hz, prm)
+    assert grd.shape == gref.shape == (nw, 2 * n, 2 * n)
+    assert np.max(np.abs(grd - gref)) <= (1e-12 if prec == "f64" else 2e-6) * np.max(np.abs(gref))

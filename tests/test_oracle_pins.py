@@ -494,3 +494,54 @@ def test_fold_reduces_the_w_error(oracle_mod, c1):
         D = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, prm)
         errs.append(np.linalg.norm((D - Dd)[c, c]) / np.linalg.norm(Dd[c, c]))
     assert errs[1] < 0.7 * errs[0], errs
+
+
+# ---------------------------------------------------------------------------------------
+# grid padding x2 (an accuracy variant): the image is the central crop of a 2n grid
+
+def test_padded_unit_visibility_is_flat_everywhere(oracle_mod):
+    """P19: with a 2n grid the taper is only evaluated for |xi| <= 1/4, so the image of one
+    unit visibility at uvw = 0 is the closed-form ratio (kernel Fourier series over its
+    transform, at xi = (j - n/2) / 2n) on every pixel, and within 7e-6 of 1 everywhere."""
+    kbm = oracle_mod.kb
+    n, dl, f, W = 64, 2e-3, 1e9, 7
+    beta = 2.34 * W
+    prm = _prm(oracle_mod, n, dl, 4, W)
+    prm.pad = 2
+    D = oracle_mod.wstack_image(np.zeros((1, 3)), np.ones(1), np.ones(1), f, prm, complex_out=True)
+    t = np.arange(W) - (W - 1) // 2
+    xi = (np.arange(n) - n // 2) / (2 * n)
+    series = (kbm.kb(t, W, beta)[None, :] * np.cos(2 * math.pi * np.outer(xi, t))).sum(1)
+    ratio = series / kbm.kb_taper(xi, W, beta)
+    assert np.max(np.abs(D - np.outer(ratio, ratio))) < 1e-13
+    assert np.max(np.abs(D - 1.0)) < 7e-6
+
+
+def test_padding_removes_the_edge_aliasing(oracle_mod, c1):
+    """P20: against the direct DFT of Eq. 1, padding leaves the inner-half error (set by the
+    w planes) unchanged and cuts the full-image error (the edge aliasing of an unpadded
+    grid) by more than 20x; the padded prediction stays the transpose of the padded imager."""
+    ds = c1
+    Dd = oracle_mod.dft_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, ds.n, ds.pixel_rad)
+    c = slice(ds.n // 4, 3 * ds.n // 4)
+    inner, full = [], []
+    for pad in (1, 2):
+        prm = _prm(oracle_mod, ds.n, ds.pixel_rad, ds.n_wplanes, ds.support)
+        prm.pad = pad
+        D = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, prm)
+        inner.append(np.linalg.norm((D - Dd)[c, c]) / np.linalg.norm(Dd[c, c]))
+        full.append(np.linalg.norm(D - Dd) / np.linalg.norm(Dd))
+    assert abs(inner[1] - inner[0]) < 0.1 * inner[0]
+    assert full[1] < full[0] / 20, full
+    sub = ds.subset(slice(0, 20000))
+    prm = _prm(oracle_mod, sub.n, sub.pixel_rad, sub.n_wplanes, sub.support)
+    prm.pad = 2
+    prm.fold = True
+    rng = np.random.default_rng(61)
+    z = rng.normal(size=sub.m) + 1j * rng.normal(size=sub.m)
+    X = rng.normal(size=(sub.n, sub.n))
+    ones = np.ones(sub.m)
+    A = oracle_mod.wstack_image(sub.uvw_m, z, ones, sub.freq_hz, prm, normalize=False)
+    y = oracle_mod.wstack_predict(sub.uvw_m, ones, sub.freq_hz, prm, X)
+    lhs, rhs = float(np.sum(A * X)), float(np.real(np.sum(z * np.conj(y))))
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
