@@ -74,6 +74,10 @@ def cols_stack_flops(n: int, nw_occ: int) -> float:
     return nw_occ * n * (5.0 * n * math.log2(n) + 8.0 * n)
 
 
+# accuracy variants applied to every plan (--fold, --pad2); empty: the plain method
+VARIANT = {}
+
+
 def run_gpu(ds, prec: str, steps: int, warmup: int):
     import torch
     import paper_2601_19714_amd as ws
@@ -83,7 +87,7 @@ def run_gpu(ds, prec: str, steps: int, warmup: int):
     uvw = torch.from_numpy(d.uvw_m).to(dev)
     vis = torch.from_numpy(d.vis).to(dev)
     wts = torch.from_numpy(d.weights).to(dev)
-    plan = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, prec, max_vis=d.m)
+    plan = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, prec, max_vis=d.m, **VARIANT)
     out = torch.empty((d.n, d.n), dtype=torch.float32 if prec == "f32" else torch.float64, device=dev)
     _, st = plan.image(uvw, vis, wts, d.freq_hz, out=out, stats=True)
     for _ in range(warmup):
@@ -120,7 +124,7 @@ def run_gpu_batch(chans, steps: int, warmup: int):
     d = chans[0]
     nch = len(chans)
     plan = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, "f32", max_vis=sum(counts),
-                   max_channels=nch)
+                   max_channels=nch, **VARIANT)
     out = torch.empty((nch, d.n, d.n), dtype=torch.float32, device=dev)
     _, st = plan.image_batch(uvw, vis, wts, counts, freqs, out=out, stats=True)
     for _ in range(warmup):
@@ -140,7 +144,7 @@ def run_gpu_batch(chans, steps: int, warmup: int):
 
     # the same call captured into a HIP graph and replayed
     gplan = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, "f32", max_vis=sum(counts),
-                    max_channels=nch)
+                    max_channels=nch, **VARIANT)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -161,7 +165,7 @@ def run_gpu_batch(chans, steps: int, warmup: int):
     gplan.close()
 
     off = np.concatenate([[0], np.cumsum(counts)])
-    single = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, "f32", max_vis=max(counts))
+    single = ws.Plan(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, "f32", max_vis=max(counts), **VARIANT)
     one = torch.empty((d.n, d.n), dtype=torch.float32, device=dev)
     sl = [slice(int(off[c]), int(off[c + 1])) for c in range(nch)]
 
@@ -229,6 +233,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 path")
+    ap.add_argument("--fold", action="store_true", help="w-folding (accuracy variant)")
+    ap.add_argument("--pad2", action="store_true", help="grid of twice the image side (accuracy variant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-planes", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -255,6 +261,10 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 5}))
         return
 
+    if args.fold:
+        VARIANT["fold_w"] = True
+    if args.pad2:
+        VARIANT["pad"] = 2
     cfg = WORKLOADS[args.workload]
     if cfg == 4:
         bench_batch(args)
@@ -306,7 +316,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": ds.name, "n_vis": m, "n": ds.n, "n_wplanes": ds.n_wplanes,
+        "config": {"workload": ds.name, "variant": dict(VARIANT), "n_vis": m, "n": ds.n, "n_wplanes": ds.n_wplanes,
                    "support": ds.support, "beta": ds.beta, "pixel_arcsec": ds.pixel_rad / synth.ARCSEC,
                    "freq_hz": ds.freq_hz, "precision": "f32"},
         "stage_ms": per_call,
@@ -437,7 +447,7 @@ def bench_batch(args):
         "metric": METRIC, "value": m / (r["ms_per_step"] / 1e3), "unit": "visibilities/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c4_batched_f32", "n_channels": len(chans), "n_vis": m,
+        "config": {"workload": "c4_batched_f32", "variant": dict(VARIANT), "n_channels": len(chans), "n_vis": m,
                    "rows_per_channel": [min(r["counts"]), max(r["counts"])], "n": d.n,
                    "n_wplanes": d.n_wplanes, "support": d.support, "freq_hz": [chans[0].freq_hz, chans[-1].freq_hz],
                    "precision": "f32"},

@@ -619,7 +619,9 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int LR2 = LR2_0 < LOG2N ? LR2_0 : LOG2N - 1;
     static constexpr int E1 = 1 << LR1, E2 = 1 << LR2;
     static constexpr int CAP1 = LOG2N >= 12 ? WSIMG_STRIP_CELLS : WSIMG_STRIP_CELLS_SMALL;
-    static constexpr int H0 = CAP1 / N < 32 ? (CAP1 / N < 1 ? 1 : CAP1 / N) : 32;   // a row at least
+    // a row at least; at most 4, so that small images still have many strips in flight and
+    // few register walks per strip (a 256^2 image: 1.18 ms with 16-row strips)
+    static constexpr int H0 = CAP1 / N < 4 ? (CAP1 / N < 1 ? 1 : CAP1 / N) : 4;
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
     static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);
     static constexpr int PX2 = sizeof(R) == 4 ? WSIMG_F32_PX2 : WSIMG_F64_PX2;
