@@ -200,14 +200,16 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
 constexpr int kReplicas = 64;
 constexpr int kLogReplicas = 6;
 
-// Ranks.  With WSIMG_KEY_WAVE_AGG = 1 (default) the lanes of a wave sharing a key elect a
-// leader that adds their count, and each lane's rank is the returned base plus the number of
-// lower lanes with the same key; the grouping uses scalar lane reads and ballots, and the
-// leaders' atomics go out together.  With 0 each lane takes its rank with its own atomic (one
-// instruction per wave, but the lanes hitting a hot bucket serialise in the cache: measured
-// 3.4x slower on 64 channels of 1024^2, where most lanes of a wave share a few buckets).
+// Ranks inside a (bucket, replica) counter.  WSIMG_KEY_WAVE_AGG selects how:
+//  2 (default): the block's rows group their keys in an LDS hash table; one global atomic per
+//     distinct key of the block, and each row's rank is that atomic's return plus its order
+//     in the table slot (C2 key stage 0.38 -> 0.30 ms, 64 channels of 1024^2 2.1 -> 1.1 ms);
+//  1: the lanes of a wave sharing a key elect a leader (a loop over the wave's distinct keys
+//     with scalar lane reads and ballots), and the leaders' atomics go out together;
+//  0: one atomic per row (the lanes hitting a hot bucket serialise in the cache: 3.4x slower
+//     than 1 on 64 channels of 1024^2, where most lanes of a wave share a few buckets).
 #ifndef WSIMG_KEY_WAVE_AGG
-#define WSIMG_KEY_WAVE_AGG 1
+#define WSIMG_KEY_WAVE_AGG 2
 #endif
 
 template <typename WT>
@@ -231,7 +233,32 @@ k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom 
         }
     }
     const uint32_t rep = blockIdx.x & (kReplicas - 1);
-#if WSIMG_KEY_WAVE_AGG
+#if WSIMG_KEY_WAVE_AGG == 2
+    // block-wide aggregation through an LDS hash table (open addressing, 2x the block's
+    // rows, so a free slot always exists): each distinct key of the block takes one atomic
+    constexpr int kSlots = 512;
+    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+    __shared__ uint32_t hkey[kSlots], hcnt[kSlots], hbase[kSlots];
+    for (int i = threadIdx.x; i < kSlots; i += blockDim.x) { hkey[i] = kEmpty; hcnt[i] = 0u; }
+    __syncthreads();
+    uint32_t slot = 0, local = 0;
+    if (kk != kEmpty) {
+        slot = (kk * 2654435761u) >> 23;          // 9-bit multiplicative hash
+        while (true) {
+            const uint32_t prev = atomicCAS(&hkey[slot], kEmpty, kk);
+            if (prev == kEmpty || prev == kk) break;
+            slot = (slot + 1) & (kSlots - 1);
+        }
+        local = atomicAdd(&hcnt[slot], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
+        const uint32_t key_i = hkey[i];
+        if (key_i != kEmpty) hbase[i] = atomicAdd(&counts[((size_t)key_i << kLogReplicas) + rep], hcnt[i]);
+    }
+    __syncthreads();
+    const uint32_t rr = kk != kEmpty ? hbase[slot] + local : 0u;
+#elif WSIMG_KEY_WAVE_AGG
     const int lane = threadIdx.x & 63;
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     unsigned long long todo = __ballot(kk != 0xFFFFFFFFu);
