@@ -682,6 +682,9 @@ template <typename R, int LOG2N> struct Shape {
 // 4e-6 of the image peak near the edges, where the taper amplifies grid rounding.)  The chunk length grows with the records the
 // strip reads (one record per lane up to NT records, at most kChunkMax), so sparse strips
 // keep every lane busy and dense ones merge long runs.
+#ifndef WSIMG_GRID_BATCH
+#define WSIMG_GRID_BATCH 4
+#endif
 #ifndef WSIMG_GRID_CHUNK_MAX
 #define WSIMG_GRID_CHUNK_MAX 32
 #endif
@@ -764,20 +767,21 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                 }
             }
         };
-        for (; r < re; ++r) {
+        // one record: bucket tracking, run bookkeeping and its taps in this walk
+        auto process = [&](const RawRec<R>& x, uint32_t r) {
             while (r >= bend) {
                 ++sp;
                 bend = offsets[(size_t)(bucket0 + sp + 1) << kLogReplicas];
             }
             int q0, p0;
             C fr, v;
-            decode_record<R>(fetch_record<R>(rec_cell, rec, r), sp, LOG2H, q0, p0, fr, v);
+            decode_record<R>(x, sp, LOG2H, q0, p0, fr, v);
             if (q0 != cq || p0 != cp) {
                 flush();
                 cq = q0;
                 cp = p0;
             }
-            if (rlo + RW - 1 < p0 || rlo > p0 + W - 1) continue;     // no tap row in this walk
+            if (rlo + RW - 1 < p0 || rlo > p0 + W - 1) return;       // no tap row in this walk
             R gx[WMAX];
 #pragma unroll
             for (int a = 0; a < WMAX; ++a)
@@ -797,6 +801,20 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                     }
                 }
             }
+        };
+        // records are fetched WSIMG_GRID_BATCH at a time, so that several loads are in flight
+        constexpr uint32_t KB = WSIMG_GRID_BATCH;
+        for (uint32_t left = re - r; left > 0;) {
+            const uint32_t cnt = left < KB ? left : KB;
+            RawRec<R> buf[KB];
+#pragma unroll
+            for (uint32_t i = 0; i < KB; ++i)
+                if (i < cnt) buf[i] = fetch_record<R>(rec_cell, rec, r + i);
+#pragma unroll
+            for (uint32_t i = 0; i < KB; ++i)
+                if (i < cnt) process(buf[i], r + i);
+            r += cnt;
+            left -= cnt;
         }
         flush();
     }
