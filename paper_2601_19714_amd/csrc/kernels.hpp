@@ -60,10 +60,23 @@ struct Scalars {
 };
 
 // The gridding work list of occupied strips of all channels: heavy ones from the front,
-// light ones from the back; next is the persistent kernel's fetch counter.
+// light ones from the back; next is the persistent kernel's fetch counter, n_split the number
+// of strips split into parts (below).
 struct WorkList {
-    unsigned int n_heavy, n_light, next, pad;
+    unsigned int n_heavy, n_light, next, n_split;
 };
+
+// Heavy strips are split.  With `share` the record visits of the call over the gridding
+// work-groups (each work-group's fair share, at least kMinPart), a strip of more than
+// 2 * share visits would outlast the rest of the grid alone, so it is gridded as
+// P = min(kMaxParts, ceil(visits / share)) parts by different work-groups (each a contiguous
+// share of its records), which add their float64 strips into a global slot; the work-group
+// that completes the last part takes the sum and runs the row FFT.  At most kMaxSplit strips
+// per call are split (the slots' memory); the rest run whole.  A list entry's companion
+// word: slot << 16 | part << 8 | parts (parts = 1: not split).
+constexpr uint32_t kMinPart = 4096;
+constexpr uint32_t kMaxParts = 32;
+constexpr uint32_t kMaxSplit = 512;
 
 struct Partial {
     double wmin, wmax, sumw;
@@ -371,8 +384,8 @@ constexpr uint32_t kHeavyStrip = 4096;
 
 __global__ void __launch_bounds__(256)
 k_occupancy(int nch, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __restrict__ occ,
-            uint8_t* __restrict__ plane_occ, uint32_t* __restrict__ list, Scalars* __restrict__ sc,
-            WorkList* __restrict__ wl) {
+            uint8_t* __restrict__ plane_occ, uint32_t* __restrict__ list, uint32_t* __restrict__ list_aux,
+            uint32_t list_cap, uint32_t share, Scalars* __restrict__ sc, WorkList* __restrict__ wl) {
     const int total = nch * g.nb1;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t o = 0, po = 0, visits = 0;
@@ -393,19 +406,32 @@ k_occupancy(int nch, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __re
         }
     }
     const int lane = threadIdx.x & 63;
-    const unsigned long long heavy = __ballot(o && visits > kHeavyStrip);
     const unsigned long long light = __ballot(o && visits <= kHeavyStrip);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t hbase = 0, lbase = 0;
-    if (lane == 0) {
-        if (heavy) hbase = atomicAdd(&wl->n_heavy, (unsigned)__popcll(heavy));
-        if (light) lbase = atomicAdd(&wl->n_light, (unsigned)__popcll(light));
-    }
-    hbase = __shfl(hbase, 0, 64);
+    uint32_t lbase = 0;
+    if (lane == 0 && light) lbase = atomicAdd(&wl->n_light, (unsigned)__popcll(light));
     lbase = __shfl(lbase, 0, 64);
-    if (o) {
-        if (visits > kHeavyStrip) list[hbase + __popcll(heavy & below)] = (uint32_t)b;
-        else list[total - 1 - (lbase + __popcll(light & below))] = (uint32_t)b;
+    if (o && visits <= kHeavyStrip) {
+        const uint32_t at = list_cap - 1 - (lbase + __popcll(light & below));
+        list[at] = (uint32_t)b;
+        list_aux[at] = 1u;
+    } else if (o) {
+        // heavy: one entry, or one per part when split (heavy strips are few: one atomic each)
+        uint32_t parts = 1, slot = 0;
+        if (visits > 2 * share) {
+            slot = atomicAdd(&wl->n_split, 1u);
+            if (slot < kMaxSplit) {
+                parts = (visits + share - 1) / share;
+                parts = parts > kMaxParts ? kMaxParts : parts;
+            } else {
+                slot = 0;
+            }
+        }
+        const uint32_t at = atomicAdd(&wl->n_heavy, parts);
+        for (uint32_t p = 0; p < parts; ++p) {
+            list[at + p] = (uint32_t)b;
+            list_aux[at + p] = (slot << 16) | (p << 8) | parts;
+        }
     }
     // per-channel counts: one atomic per wave when the wave lies in one channel
     const int c0 = __shfl(c, 0, 64);
@@ -702,13 +728,17 @@ template <typename R, int WMAX> struct WalkRows {
 };
 
 // One occupied strip (plane k of channel c, strip s) by the whole work-group.
+// aux: the list entry's companion word (parts = 1 when not split); split_acc / split_done:
+// the slots of split strips (float64 strip sums, completed-part counters).
 template <typename R, bool FFT, int LOG2N, int WMAX>
 __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, unsigned char* smem_raw,
                                            const uint32_t* __restrict__ offsets,
                                            const uint32_t* __restrict__ rec_cell,
                                            const void* __restrict__ rec,
                                            const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
-                                           typename Cx<R>::T* __restrict__ out) {
+                                           typename Cx<R>::T* __restrict__ out, uint32_t aux = 1u,
+                                           double2* __restrict__ split_acc = nullptr,
+                                           uint32_t* __restrict__ split_done = nullptr) {
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
     constexpr int n = SH::N, H = SH::H, NT = SH::NT1, nmask = n - 1;
@@ -728,8 +758,15 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
     if (s_lo < 0) s_lo = 0;
     constexpr int shift = FFT ? (n >> 1) : 0;   // place cell q at (q + n/2) mod n: the centring
     const int bucket0 = c * g.nb1 + k * g.S;
-    const uint32_t vbeg = offsets[(size_t)(bucket0 + s_lo) << kLogReplicas];
-    const uint32_t vend = offsets[(size_t)(bucket0 + s + 1) << kLogReplicas];
+    uint32_t vbeg = offsets[(size_t)(bucket0 + s_lo) << kLogReplicas];
+    uint32_t vend = offsets[(size_t)(bucket0 + s + 1) << kLogReplicas];
+    const uint32_t parts = aux & 0xFFu, part = (aux >> 8) & 0xFFu, slot = aux >> 16;
+    if (parts > 1) {       // this part's share of the strip's records
+        const uint64_t len = vend - vbeg;
+        const uint32_t pb = vbeg + (uint32_t)(len * part / parts), pe = vbeg + (uint32_t)(len * (part + 1) / parts);
+        vbeg = pb;
+        vend = pe;
+    }
     const uint32_t nv = vend - vbeg;
     uint32_t chunk = nv / NT;
     chunk = chunk < 1u ? 1u : (chunk > kChunkMax ? kChunkMax : chunk);
@@ -820,6 +857,31 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
     }
     __syncthreads();
 
+    if (parts > 1) {
+        // add this part into the strip's slot; the work-group completing the last part takes
+        // the sum (and leaves the slot and its counter zero for the next call)
+        __shared__ int s_last;
+        double2* gacc = split_acc + (size_t)slot * SH::LDS1;
+        for (int e = tid; e < SH::LDS1; e += NT) {
+            const double2 a = acc[e];
+            if (a.x != 0.0) unsafeAtomicAdd(&gacc[e].x, a.x);
+            if (a.y != 0.0) unsafeAtomicAdd(&gacc[e].y, a.y);
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s_last = atomicAdd(&split_done[slot], 1u) == parts - 1 ? 1 : 0;
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        unsigned long long* gbits = reinterpret_cast<unsigned long long*>(gacc);
+        for (int e = tid; e < SH::LDS1; e += NT) {
+            acc[e] = make_double2(__longlong_as_double((long long)atomicExch(&gbits[2 * e], 0ull)),
+                                  __longlong_as_double((long long)atomicExch(&gbits[2 * e + 1], 0ull)));
+        }
+        if (tid == 0) atomicExch(&split_done[slot], 0u);
+        __syncthreads();
+    }
+
     if constexpr (FFT) {
         if constexpr (sizeof(R) == 4) {
             // float64 strip -> float32 strip in the same LDS, in two halves: the floats of the
@@ -894,29 +956,35 @@ k_grid_only(Geom g, const uint32_t* __restrict__ offsets, const uint8_t* __restr
 // list is exhausted.
 template <typename R, int LOG2N, int WMAX>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
-k_grid_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
+k_grid_rows(Geom g, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
+            const uint32_t* __restrict__ list_aux, uint32_t list_cap,
             const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
             const void* __restrict__ rec, const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
-            typename Cx<R>::T* __restrict__ out) {
+            typename Cx<R>::T* __restrict__ out, double2* __restrict__ split_acc,
+            uint32_t* __restrict__ split_done) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item;
-    const int total = nch * g.nb1;
+    __shared__ uint32_t item_aux;
     const unsigned n_heavy = wl->n_heavy, n_light = wl->n_light;
     while (true) {
         if (threadIdx.x == 0) {
             const unsigned i = atomicAdd(&wl->next, 1u);
             int b = -1;
-            if (i < n_heavy) b = (int)list[i];
-            else if (i - n_heavy < n_light) b = (int)list[total - 1 - (int)(i - n_heavy)];
+            uint32_t x = 1u;
+            if (i < n_heavy) { b = (int)list[i]; x = list_aux[i]; }
+            else if (i - n_heavy < n_light) b = (int)list[list_cap - 1 - (i - n_heavy)];
             item = b;
+            item_aux = x;
         }
         __syncthreads();
         const int b = item;
+        const uint32_t aux = item_aux;
         __syncthreads();
         if (b < 0) break;
         const int c = b / g.nb1, bb = b - c * g.nb1;
         const int k = bb / g.S, s = bb - k * g.S;
-        grid_strip<R, true, LOG2N, WMAX>(g, c, k, s, smem_raw, offsets, rec_cell, rec, kbc, opaque_ptr(tw), out);
+        grid_strip<R, true, LOG2N, WMAX>(g, c, k, s, smem_raw, offsets, rec_cell, rec, kbc, opaque_ptr(tw), out,
+                                         aux, split_acc, split_done);
         __syncthreads();
     }
 }
@@ -1205,7 +1273,7 @@ __device__ __forceinline__ void degrid_strip(const Geom& g, int c, int k, int s,
                                              const R* __restrict__ kbc,
                                              const typename Cx<R>::T* __restrict__ tw,
                                              const typename Cx<R>::T* __restrict__ inter,
-                                             typename Cx<R>::T* __restrict__ vis_out) {
+                                             typename Cx<R>::T* __restrict__ vis_out, uint32_t aux) {
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
     constexpr int n = SH::N, H = SH::H, NT = SH::NT1, nmask = n - 1, hn = n >> 1;
@@ -1237,9 +1305,21 @@ __device__ __forceinline__ void degrid_strip(const Geom& g, int c, int k, int s,
     int s_lo = (row0 - (W - 1)) >> LOG2H;
     if (s_lo < 0) s_lo = 0;
     const int bucket0 = c * g.nb1 + k * g.S;
+    // a split strip: every part transforms the strip and degrids its share of the records
+    uint32_t pb = offsets[(size_t)(bucket0 + s_lo) << kLogReplicas];
+    uint32_t pe = offsets[(size_t)(bucket0 + s + 1) << kLogReplicas];
+    const uint32_t parts = aux & 0xFFu, part = (aux >> 8) & 0xFFu;
+    if (parts > 1) {
+        const uint64_t len = pe - pb;
+        const uint32_t b0 = pb;
+        pb = b0 + (uint32_t)(len * part / parts);
+        pe = b0 + (uint32_t)(len * (part + 1) / parts);
+    }
     for (int sp = s_lo; sp <= s; ++sp) {
-        const uint32_t beg = offsets[(size_t)(bucket0 + sp) << kLogReplicas];
-        const uint32_t end = offsets[(size_t)(bucket0 + sp + 1) << kLogReplicas];
+        uint32_t beg = offsets[(size_t)(bucket0 + sp) << kLogReplicas];
+        uint32_t end = offsets[(size_t)(bucket0 + sp + 1) << kLogReplicas];
+        beg = beg > pb ? beg : pb;
+        end = end < pe ? end : pe;
         for (uint32_t r = beg + tid; r < end; r += NT) {
             int q0, p0;
             C fr, v;
@@ -1280,31 +1360,35 @@ __device__ __forceinline__ void degrid_strip(const Geom& g, int c, int k, int s,
 // Persistent over the work list of occupied strips of all channels (as k_grid_rows).
 template <typename R, int LOG2N, int WMAX>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT1))
-k_adj_rows(Geom g, int nch, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
+k_adj_rows(Geom g, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
+           const uint32_t* __restrict__ list_aux, uint32_t list_cap,
            const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
            const void* __restrict__ rec, const uint32_t* __restrict__ rec_idx, const R* __restrict__ kbc,
            const typename Cx<R>::T* __restrict__ tw, const typename Cx<R>::T* __restrict__ inter,
            typename Cx<R>::T* __restrict__ vis_out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item;
-    const int total = nch * g.nb1;
+    __shared__ uint32_t item_aux;
     const unsigned n_heavy = wl->n_heavy, n_light = wl->n_light;
     while (true) {
         if (threadIdx.x == 0) {
             const unsigned i = atomicAdd(&wl->next, 1u);
             int b = -1;
-            if (i < n_heavy) b = (int)list[i];
-            else if (i - n_heavy < n_light) b = (int)list[total - 1 - (int)(i - n_heavy)];
+            uint32_t x = 1u;
+            if (i < n_heavy) { b = (int)list[i]; x = list_aux[i]; }
+            else if (i - n_heavy < n_light) b = (int)list[list_cap - 1 - (i - n_heavy)];
             item = b;
+            item_aux = x;
         }
         __syncthreads();
         const int b = item;
+        const uint32_t aux = item_aux;
         __syncthreads();
         if (b < 0) break;
         const int c = b / g.nb1, bb = b - c * g.nb1;
         const int k = bb / g.S, s = bb - k * g.S;
         degrid_strip<R, LOG2N, WMAX>(g, c, k, s, smem_raw, offsets, rec_cell, rec, rec_idx, kbc,
-                                     opaque_ptr(tw), inter, vis_out);
+                                     opaque_ptr(tw), inter, vis_out, aux);
         __syncthreads();
     }
 }

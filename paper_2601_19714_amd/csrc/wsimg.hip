@@ -68,7 +68,11 @@ struct wsimg_plan {
     void* staging_graph = nullptr;
     uint32_t *counts = nullptr, *offsets = nullptr, *tile_sums = nullptr;
     uint8_t *occ = nullptr, *plane_occ = nullptr;
-    uint32_t* list = nullptr;      // work list of occupied strips
+    uint32_t* list = nullptr;      // work list of occupied strips (heavy ones split into parts)
+    uint32_t* list_aux = nullptr;  // each entry's part word
+    uint32_t list_cap = 0;
+    double2* split_acc = nullptr;  // float64 sums of split strips (zero between calls)
+    uint32_t* split_done = nullptr;
     int persist_blocks = 256;      // work-groups of the persistent gridding kernel
     uint32_t *key = nullptr, *rank = nullptr, *rec_cell = nullptr, *rec_cell2 = nullptr;
     uint32_t* rec_idx = nullptr;   // input row of each record (prediction)
@@ -222,8 +226,9 @@ wsimg_status launch_grid_w(wsimg_plan* pl, int nch, bool fft, void* out) {
     const Geom g = pl->g;
     if (fft) {
         hipLaunchKernelGGL((k_grid_rows<R, LOG2N, WMAX>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1),
-                           pl->lds1, pl->stream, g, nch, pl->worklist, pl->list, pl->offsets, pl->rec_cell2,
-                           (const void*)pl->rec2, (const R*)pl->kbc, (const C*)pl->tw, (C*)out);
+                           pl->lds1, pl->stream, g, pl->worklist, pl->list, pl->list_aux, pl->list_cap,
+                           pl->offsets, pl->rec_cell2, (const void*)pl->rec2, (const R*)pl->kbc, (const C*)pl->tw,
+                           (C*)out, pl->split_acc, pl->split_done);
     } else {
         hipLaunchKernelGGL((k_grid_only<R, LOG2N, WMAX>), dim3((unsigned)(g.nw * g.S), (unsigned)nch),
                            dim3(pl->nt1), pl->lds1, pl->stream, g, pl->offsets, pl->occ, pl->rec_cell2,
@@ -285,7 +290,8 @@ wsimg_status launch_adj_rows_w(wsimg_plan* pl, int nch, void* vis_out) {
     using C = typename Cx<R>::T;
     const size_t lds = (size_t)Shape<R, LOG2N>::LDS1 * sizeof(C);
     hipLaunchKernelGGL((k_adj_rows<R, LOG2N, WMAX>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1), lds,
-                       pl->stream, pl->g, nch, pl->worklist, pl->list, pl->offsets, pl->rec_cell,
+                       pl->stream, pl->g, pl->worklist, pl->list, pl->list_aux, pl->list_cap, pl->offsets,
+                       pl->rec_cell,
                        (const void*)pl->rec, (const uint32_t*)pl->rec_idx, (const R*)pl->kbc,
                        (const C*)pl->tw, (const C*)pl->inter, (C*)vis_out);
     WS_LAUNCH_CHECK("adj_rows");
@@ -439,8 +445,13 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     WS_LAUNCH_CHECK("scan_top");
     hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(256), 0, s, ncnt, pl->counts, pl->tile_sums, pl->offsets);
     WS_LAUNCH_CHECK("scan_down");
+    // each gridding work-group's share of the call's record visits (a row's taps reach about
+    // (W + H - 2) / H + 1 strips)
+    const int64_t visits = bt.total * (int64_t)((g.support + g.H - 2) / g.H + 1);
+    const int64_t share = std::max<int64_t>(kMinPart, visits / std::max(1, pl->persist_blocks));
     hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nbk, 256)), dim3(256), 0, s, nch, pl->offsets, g,
-                       pl->occ, pl->plane_occ, pl->list, pl->scalars, pl->worklist);
+                       pl->occ, pl->plane_occ, pl->list, pl->list_aux, pl->list_cap,
+                       (uint32_t)std::min<int64_t>(share, 0x3FFFFFFF), pl->scalars, pl->worklist);
     WS_LAUNCH_CHECK("occupancy");
     if (auto r = st.after(3)) return r;
 
@@ -621,7 +632,11 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     ALLOC(offsets, sizeof(uint32_t) * (nbt * kReplicas + 1), "offsets");
     ALLOC(tile_sums, sizeof(uint32_t) * ((nbt * kReplicas + kScanTile - 1) / kScanTile), "scan tiles");
     ALLOC(occ, nbt, "occupancy");
-    ALLOC(list, sizeof(uint32_t) * nbt, "strip work list");
+    pl->list_cap = (uint32_t)(nbt + (size_t)kMaxSplit * kMaxParts);
+    ALLOC(list, sizeof(uint32_t) * pl->list_cap, "strip work list");
+    ALLOC(list_aux, sizeof(uint32_t) * pl->list_cap, "strip work list parts");
+    ALLOC(split_acc, (size_t)kMaxSplit * pl->lds1, "split strip sums");
+    ALLOC(split_done, sizeof(uint32_t) * kMaxSplit, "split strip counters");
     ALLOC(plane_occ, (size_t)g.nw * mc, "plane occupancy");
     ALLOC(key, sizeof(uint32_t) * mv, "keys");
     ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
@@ -649,6 +664,12 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
         if (e != hipSuccess) { pl->staged_ev = nullptr; r = fail(WSIMG_E_HIP, "hipEventCreate failed"); }
     }
     if (!r) r = f32 ? upload_tables<float>(pl) : upload_tables<double>(pl);
+    if (!r) {
+        hipError_t e = hipMemset(pl->split_acc, 0, (size_t)kMaxSplit * pl->lds1);
+        if (e == hipSuccess) e = hipMemset(pl->split_done, 0, sizeof(uint32_t) * kMaxSplit);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) r = fail(WSIMG_E_HIP, std::string("clearing split slots: ") + hipGetErrorString(e));
+    }
     if (r) { release(pl); delete pl; return r; }
     *out = pl;
     return WSIMG_OK;
