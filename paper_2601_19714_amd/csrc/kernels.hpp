@@ -657,11 +657,36 @@ static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
 #ifndef WSIMG_F64_PX2
 #define WSIMG_F64_PX2 4096
 #endif
+// image columns per stacking block (0: all B columns of a layout block).  float: one, so that
+// a block is 512 threads for a 4096-point column and two blocks share a CU (their barriers
+// overlap); measured 1.44 -> 1.26 ms on a 4096^2 image of 32 planes
+#ifndef WSIMG_F32_BS
+#define WSIMG_F32_BS 1
+#endif
+#ifndef WSIMG_F64_BS
+#define WSIMG_F64_BS 0
+#endif
+// 1: stacking blocks that share layout blocks are placed on one XCD (below)
+#ifndef WSIMG_COLS_XCD_MAP
+#define WSIMG_COLS_XCD_MAP 1
+#endif
+// 1: the stacking pass runs its FFT passes out of place between two LDS buffers (one barrier
+// per pass instead of two, and none at the end of a plane), where both buffers fit
+#ifndef WSIMG_COLS_PINGPONG
+#define WSIMG_COLS_PINGPONG 0
+#endif
+// 1: the stacking pass keeps the per-pixel n - 1 values in registers, not in LDS
+#ifndef WSIMG_COLS_NM1_REGS
+#define WSIMG_COLS_NM1_REGS 0
+#endif
 // 1: the stacking pass re-reads its twiddles every plane instead of keeping them in
 // registers across planes (measured: keeping them is faster at every size timed)
 #ifndef WSIMG_COLS_TW_OPAQUE
 #define WSIMG_COLS_TW_OPAQUE 0
 #endif
+
+// bytes of the stacking pass's LDS plane-flag table: the largest plane count a plan takes
+constexpr size_t kPlaneTab = 4096;
 
 template <typename R, int LOG2N> struct Shape {
     static constexpr int N = 1 << LOG2N;
@@ -678,17 +703,29 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
     static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);
     static constexpr int PX2 = sizeof(R) == 4 ? WSIMG_F32_PX2 : WSIMG_F64_PX2;
+    // the intermediate holds B columns side by side per row (the gridding pass's write unit and
+    // the prediction's column block); a stacking block takes BS <= B of them
     static constexpr int B0 = PX2 / N < N / 2 ? PX2 / N : N / 2;   // at most half a (padded) grid
     static constexpr int B = B0 < 1 ? 1 : B0;
-    static constexpr int NT2 = (B * N / E2) < 64 ? 64 : (B * N / E2);
+    static constexpr int BS0 = sizeof(R) == 4 ? WSIMG_F32_BS : WSIMG_F64_BS;
+    static constexpr int BS = (BS0 <= 0 || BS0 > B) ? B : BS0;
+    static_assert((BS & (BS - 1)) == 0, "stacking columns per block: a power of two");
+    static constexpr int NT2 = (BS * N / E2) < 64 ? 64 : (BS * N / E2);   // stacking
+    static constexpr int NT2A = (B * N / E2) < 64 ? 64 : (B * N / E2);    // prediction column pass
     static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
     static constexpr size_t LDS1_BYTES = (size_t)LDS1 * sizeof(double2);   // float64 accumulation
     static constexpr int LDS2 = lds_padded_elems_c(B * N);                 // complex elements
-    // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer
-    static constexpr bool NM1_LDS =
-        (size_t)LDS2 * 2 * sizeof(R) + sizeof(double) * E2 * NT2 <= 160 * 1024;
-    static constexpr size_t LDS2_BYTES =
-        (size_t)LDS2 * 2 * sizeof(R) + (NM1_LDS ? sizeof(double) * E2 * NT2 : 0);
+    static constexpr size_t LDS2_BYTES = (size_t)LDS2 * 2 * sizeof(R);      // column pass of prediction
+    static constexpr int LDS2S = lds_padded_elems_c(BS * N);               // stacking FFT buffer
+    static constexpr size_t LDS2S_BUF = (size_t)LDS2S * 2 * sizeof(R);
+    // stacking: two FFT buffers when out-of-place passes are on and both fit
+    static constexpr int NBUF2 = (WSIMG_COLS_PINGPONG && 2 * LDS2S_BUF <= 160 * 1024) ? 2 : 1;
+    // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer(s) and the
+    // plane flags (kPlaneTab bytes, after everything else)
+    static constexpr bool NM1_LDS = !WSIMG_COLS_NM1_REGS &&
+        NBUF2 * LDS2S_BUF + sizeof(double) * E2 * NT2 + kPlaneTab <= 160 * 1024;
+    static constexpr size_t PTAB_OFF = NBUF2 * LDS2S_BUF + (NM1_LDS ? sizeof(double) * E2 * NT2 : 0);
+    static constexpr size_t LDS2S_BYTES = PTAB_OFF + kPlaneTab;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -1008,55 +1045,101 @@ k_grid_rows(Geom g, WorkList* __restrict__ wl, const uint32_t* __restrict__ list
 #endif
 template <typename R> struct Pass2Prefetch { static constexpr bool value = sizeof(R) == 4 && WSIMG_COLS_PREFETCH; };
 
+// The stacking pass's strip flags: for channel c, plane k and b < N / 2^LR, bit m of
+// flags[(c nw + k) N/2^LR + b] is set when row b + m N/2^LR of the plane lies in an occupied
+// strip.  A stacking thread's first pass reads rows b + m N/2^LR (m < 2^LR), so one load per
+// plane gives it the flags of all of them.
+__global__ void __launch_bounds__(256)
+k_stack_flags(Geom g, int nch, int lr, const uint8_t* __restrict__ occ, uint16_t* __restrict__ flags) {
+    const int nr = g.n >> lr;
+    const int64_t total = (int64_t)nch * g.nw * nr;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int b = (int)(i % nr);
+    const uint8_t* o = occ + (i / nr) * g.S;
+    uint32_t bits = 0;
+    for (int m = 0; m < (1 << lr); ++m) bits |= (o[(b + m * nr) >> g.log2H] ? 1u : 0u) << m;
+    flags[i] = (uint16_t)bits;
+}
+
+// The rows of occupied strips (zero elsewhere) of one plane's block: src is the block's
+// first element in the intermediate, toff the thread's element of row b (b B + its column), fl
+// the thread's flag word of the plane.  Slot m holds
+// row (b + m N/2^LR + N/2) mod N, i.e. flag bit (m + 2^LR / 2) mod 2^LR.
 template <typename R, int LOG2N, int LR, int B>
-__device__ __forceinline__ void pass2_load(const typename Cx<R>::T* __restrict__ src,
-                                           const uint8_t* __restrict__ occk, int tid, bool active,
-                                           int log2H, typename Cx<R>::T* x) {
+__device__ __forceinline__ void pass2_data(const typename Cx<R>::T* __restrict__ src, uint32_t fl,
+                                           uint32_t toff, typename Cx<R>::T* x) {
     using C = typename Cx<R>::T;
-    constexpr int n = 1 << LOG2N, hn = n >> 1, nr = n >> LR;
-    const int b = tid / B;
+    constexpr int E = 1 << LR, nr = (1 << LOG2N) >> LR;
 #pragma unroll
-    for (int m = 0; m < (1 << LR); ++m) {
+    for (int m = 0; m < E; ++m) {
         x[m] = cmake<C>((R)0, (R)0);
-        const int pp = b + m * nr;
-        const int p = (pp + hn) & (n - 1);
-        if (active && occk[p >> log2H]) x[m] = src[m * nr * B + tid];
+        if (fl & (1u << ((m + E / 2) & (E - 1)))) x[m] = src[(uint32_t)(m * nr * B) + toff];
     }
 }
 
-// Waves per SIMD the stacking kernel is compiled for (0: the compiler's choice).  Asking for
-// more caps its registers so that two work-groups fit on a CU.
-#ifndef WSIMG_COLS_WAVES_PER_EU
-#define WSIMG_COLS_WAVES_PER_EU 0
+// Waves per SIMD the stacking kernel is compiled for (0: the compiler's choice).  float: 4,
+// which caps its registers at 128 so that two 512-thread blocks fit on a CU.
+#ifndef WSIMG_F32_COLS_WAVES_PER_EU
+#define WSIMG_F32_COLS_WAVES_PER_EU 4
 #endif
+#ifndef WSIMG_F64_COLS_WAVES_PER_EU
+#define WSIMG_F64_COLS_WAVES_PER_EU 0
+#endif
+template <typename R> struct ColsWaves {
+    static constexpr int value = sizeof(R) == 4 ? WSIMG_F32_COLS_WAVES_PER_EU : WSIMG_F64_COLS_WAVES_PER_EU;
+};
+
+// Stacking block index -> block of BS image columns.  G = B / BS blocks read the same layout
+// blocks of the intermediate (each B-column row chunk); work-groups go to the 8 XCDs round-robin,
+// so the G of a layout block are given indices of one XCD, dispatched close together, and the
+// chunks fetched by the first are read by the others from that XCD's L2.
+template <int G> __device__ __forceinline__ int stack_block(int bid, int nblk) {
+    if constexpr (G == 1 || !WSIMG_COLS_XCD_MAP) {
+        return bid;
+    } else {
+        if (nblk % (8 * G) != 0) return bid;
+        const int xcd = bid & 7, slot = bid >> 3;
+        return ((((slot / G) << 3) + xcd) * G) + (slot % G);
+    }
+}
 
 // PAD: the grid is padded (the image is its central crop); without it the crop logic folds away.
 template <typename R, int LOG2N, bool PAD>
-__global__ void __launch_bounds__((Shape<R, LOG2N>::NT2), WSIMG_COLS_WAVES_PER_EU)
-k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ occ,
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT2), (ColsWaves<R>::value))
+k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict__ sflags,
              const uint8_t* __restrict__ plane_occ, const typename Cx<R>::T* __restrict__ inter,
              const typename Cx<R>::T* __restrict__ tw, const R* __restrict__ inv_taper,
              R* __restrict__ image) {
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
     constexpr int n = SH::N, nmask = n - 1, hn = n >> 1;
-    constexpr int B = SH::B, NT = SH::NT2, LOG2B = Log2Of<B>::value_any;
-    constexpr int elems = B * n;
+    // B: columns per layout block of the intermediate; BS: columns of this block
+    constexpr int B = SH::B, BS = SH::BS, NT = SH::NT2, LOG2B = Log2Of<B>::value_any;
+    constexpr int LOG2BS = Log2Of<BS>::value_any;
+    constexpr int elems = BS * n;
     constexpr int LR = SH::LR2, E = SH::E2;
     static_assert(LOG2N > LR, "image side must exceed the base radix");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* lds = reinterpret_cast<C*>(smem_raw);
-    // n - 1 of each output slot: in LDS after the FFT buffer (nm1s[s * NT + tid]) when it
+    constexpr bool PP = SH::NBUF2 == 2;
+    C* lds0 = reinterpret_cast<C*>(smem_raw);
+    C* lds1 = lds0 + (PP ? SH::LDS2S : 0);
+    // n - 1 of each output slot: in LDS after the FFT buffer(s) (nm1s[s * NT + tid]) when it
     // fits there, else in registers
-    double* nm1s = reinterpret_cast<double*>(lds + SH::LDS2);
+    double* nm1s = reinterpret_cast<double*>(lds0 + SH::NBUF2 * SH::LDS2S);
     double nm1r[SH::NM1_LDS ? 1 : E];
     nm1r[0] = 0.0;
-    const int jb = blockIdx.x, c = blockIdx.y;
+    const int jb = stack_block<B / BS>(blockIdx.x, gridDim.x), c = blockIdx.y;
     const int crop = PAD ? g.crop : 0, nimg = PAD ? g.n_img : n;
     const int tid = threadIdx.x;
-    const bool first_active = tid < (elems >> LR);
+    // every thread takes part in the first pass unless the block was widened to a wave
+    const bool first_active = (NT == (elems >> LR)) || tid < (elems >> LR);
     const uint8_t* pocc = plane_occ + (size_t)c * g.nw;
-    const uint8_t* socc = occ + (size_t)c * g.nb1;
+    constexpr int nr = n >> LR;
+    // the channel's flag words (uniform) and this thread's word within a plane
+    const uint16_t* sfl = sflags + (size_t)c * g.nw * nr;
+    const uint32_t fb = (uint32_t)(tid / BS);
+    const uint32_t toff = fb * B + (uint32_t)(tid % BS);
     const size_t plane_elems = PAD ? g.plane_elems : ((size_t)1 << (2 * LOG2N));
     const typename Cx<R>::T* cin = inter + (size_t)c * g.nw * plane_elems;
 
@@ -1069,8 +1152,8 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
         if constexpr (sizeof(R) == 4) comp[s] = (R)0;
         int col, ip;
         double v = 0.0;
-        if (last_slot<LOG2N, LR, B, NT>(tid, s, col, ip)) {
-            const int i = ((ip + hn) & nmask) - crop, j = (jb << LOG2B) + col;   // image pixel
+        if (last_slot<LOG2N, LR, BS, NT>(tid, s, col, ip)) {
+            const int i = ((ip + hn) & nmask) - crop, j = (jb << LOG2BS) + col;   // image pixel
             if (!PAD || (i >= 0 && i < nimg)) {
                 const double l = (double)(j - (nimg >> 1)) * g.pixel, m = (double)(i - (nimg >> 1)) * g.pixel;
                 const double r2 = m * m + l * l;
@@ -1082,34 +1165,64 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
     }
     const double w_lo = sc[c].w_lo, dw = sc[c].dw, sum_w = sc[c].sum_w;
 
-    int k = 0;
-    while (k < g.nw && !pocc[k]) ++k;
+    // the channel's plane flags, copied to LDS once (read by every plane step)
+    uint8_t* ptab = reinterpret_cast<uint8_t*>(smem_raw) + SH::PTAB_OFF;
+    for (int i = tid; i < g.nw; i += NT) ptab[i] = pocc[i];
+    __syncthreads();
+    auto next_plane = [&](int k0) {
+        while (k0 < g.nw && !ptab[k0]) ++k0;
+        return k0;
+    };
+    // the block's first column within its layout block
+    const int j0 = jb << LOG2BS;
+    const C* cblk = cin + (size_t)(j0 >> LOG2B) * B * n + (j0 & (B - 1));
+
+    // out-of-place passes: a plane's first pass writes buffer pp; the passes after it alternate
+    constexpr int NMID = RangePasses<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L>::value;
+    int pp = 0;
+    // planes k (in x), kn (its data in pf, loaded one plane ahead) and kn2 (its strip flags
+    // in fl, loaded two planes ahead)
+    int k = next_plane(0);
+    int kn = k < g.nw ? next_plane(k + 1) : g.nw;
     C x[E], pf[E];
-    if (k < g.nw)
-        pass2_load<R, LOG2N, LR, B>(cin + (size_t)k * plane_elems + (size_t)jb * elems,
-                                socc + (size_t)k * g.S, tid, first_active, g.log2H, pf);
+    uint32_t fl = 0;
+    if (k < g.nw) {
+        if (first_active) fl = sfl[(uint32_t)k * nr + fb];
+        pass2_data<R, LOG2N, LR, B>(cblk + (size_t)k * plane_elems, fl, toff, pf);
+        fl = (first_active && kn < g.nw) ? sfl[(uint32_t)kn * nr + fb] : 0u;
+    }
     while (k < g.nw) {
-        int kn = k + 1;
-        while (kn < g.nw && !pocc[kn]) ++kn;
+        const int kn2 = kn < g.nw ? next_plane(kn + 1) : g.nw;
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = pf[m];
         if constexpr (Pass2Prefetch<R>::value) {
-            if (kn < g.nw)
-                pass2_load<R, LOG2N, LR, B>(cin + (size_t)kn * plane_elems + (size_t)jb * elems,
-                                        socc + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
+            if (kn < g.nw) {
+                pass2_data<R, LOG2N, LR, B>(cblk + (size_t)kn * plane_elems, fl, toff, pf);
+                fl = (first_active && kn2 < g.nw) ? sfl[(uint32_t)kn2 * nr + fb] : 0u;
+            }
         }
         // first pass: radix E with L = 1 (no twiddles), registers to LDS
+        C* la = pp ? lds1 : lds0;
+        C* lb = pp ? lds0 : lds1;
         if (first_active) {
             dft_small<E>(x);
-            const int col = tid % B, b = tid / B;
+            const int col = tid % BS, b = tid / BS;
             const int base = (col << LOG2N) + (b << LR);
 #pragma unroll
-            for (int m = 0; m < E; ++m) lds[lds_pad(base + m)] = x[m];
+            for (int m = 0; m < E; ++m) la[lds_pad(base + m)] = x[m];
         }
         __syncthreads();
         const C* twk = WSIMG_COLS_TW_OPAQUE ? opaque_ptr(tw) : tw;
-        stockham_range<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L, B, NT>(lds, twk);
-        fft_last_to_regs<LOG2N, LR, B, NT>(lds, twk, x);
+        if constexpr (PP) {
+            // the last pass reads lb after an odd number of middle passes, else la; the next
+            // plane's first pass writes the other buffer (its last reads had a barrier since)
+            stockham_range_pp<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L, BS, NT>(la, lb, twk);
+            fft_last_to_regs<LOG2N, LR, BS, NT>((NMID & 1) ? lb : la, twk, x);
+            if constexpr ((NMID & 1) == 0) pp ^= 1;
+        } else {
+            stockham_range<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L, BS, NT>(la, twk);
+            fft_last_to_regs<LOG2N, LR, BS, NT>(la, twk, x);
+        }
         double wk;
         {
 #pragma clang fp contract(off)
@@ -1139,12 +1252,14 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
             }
         }
         if constexpr (!Pass2Prefetch<R>::value) {
-            if (kn < g.nw)
-                pass2_load<R, LOG2N, LR, B>(cin + (size_t)kn * plane_elems + (size_t)jb * elems,
-                                        socc + (size_t)kn * g.S, tid, first_active, g.log2H, pf);
+            if (kn < g.nw) {
+                pass2_data<R, LOG2N, LR, B>(cblk + (size_t)kn * plane_elems, fl, toff, pf);
+                fl = (first_active && kn2 < g.nw) ? sfl[(uint32_t)kn2 * nr + fb] : 0u;
+            }
         }
-        __syncthreads();
+        if constexpr (!PP) __syncthreads();
         k = kn;
+        kn = kn2;
     }
 
     const bool scale_ok = g.unnormalized || sum_w > 0.0;
@@ -1152,8 +1267,8 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         int col, ip;
-        if (last_slot<LOG2N, LR, B, NT>(tid, s, col, ip)) {
-            const int i = ((ip + hn) & nmask) - crop, j = (jb << LOG2B) + col;
+        if (last_slot<LOG2N, LR, BS, NT>(tid, s, col, ip)) {
+            const int i = ((ip + hn) & nmask) - crop, j = (jb << LOG2BS) + col;
             if (!PAD || (i >= 0 && i < nimg))
                 image[(size_t)c * nimg * nimg + (size_t)i * nimg + j] =
                     scale_ok ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
@@ -1178,7 +1293,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__
 // transform per column, and the conjugate of the result is written for the rows of occupied
 // strips in the intermediate's column-block layout (row p at p' = (p + N/2) mod N).
 template <typename R, int LOG2N>
-__global__ void __launch_bounds__((Shape<R, LOG2N>::NT2))
+__global__ void __launch_bounds__((Shape<R, LOG2N>::NT2A))
 k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ occ,
            const uint8_t* __restrict__ plane_occ, const R* __restrict__ image,
            const typename Cx<R>::T* __restrict__ tw, const R* __restrict__ inv_taper,
@@ -1186,7 +1301,7 @@ k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ o
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
     constexpr int n = SH::N, nmask = n - 1, hn = n >> 1;
-    constexpr int B = SH::B, NT = SH::NT2, LOG2B = Log2Of<B>::value_any, LR = SH::LR2;
+    constexpr int B = SH::B, NT = SH::NT2A, LOG2B = Log2Of<B>::value_any, LR = SH::LR2;
     constexpr int elems = B * n;
     constexpr int PER = (elems + NT - 1) / NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -49,8 +49,9 @@ struct wsimg_plan {
     int64_t max_vis = 0;          // rows per call, all channels together
     int max_channels = 1;
     Geom g{};
-    int nt1 = 0, nt2 = 0;          // threads of the gridding and stacking work-groups
-    size_t lds1 = 0, lds2 = 0;     // their dynamic LDS bytes
+    int nt1 = 0, nt2 = 0, nt2a = 0;  // threads of the gridding, stacking and prediction column work-groups
+    int bs = 1;                      // image columns per stacking work-group
+    size_t lds1 = 0, lds2 = 0, lds2s = 0;   // their dynamic LDS bytes (lds2s: stacking)
     int64_t nb = 0;                // buckets per channel
     size_t cbytes = 0, rbytes = 0; // complex / real element bytes
     // device memory (per-channel arrays hold max_channels entries)
@@ -68,6 +69,8 @@ struct wsimg_plan {
     void* staging_graph = nullptr;
     uint32_t *counts = nullptr, *offsets = nullptr, *tile_sums = nullptr;
     uint8_t *occ = nullptr, *plane_occ = nullptr;
+    uint16_t* sflags = nullptr;    // stacking strip flags: [max_channels][nw][n >> lr2]
+    int lr2 = 3;                   // log2 of the stacking pass's base radix
     uint32_t* list = nullptr;      // work list of occupied strips (heavy ones split into parts)
     uint32_t* list_aux = nullptr;  // each entry's part word
     uint32_t list_cap = 0;
@@ -105,6 +108,10 @@ wsimg_status dev_alloc(wsimg_plan* pl, void** out, size_t bytes, const char* wha
     return WSIMG_OK;
 }
 
+inline unsigned blocks_for(int64_t count, int threads) {
+    return (unsigned)((count + threads - 1) / threads);
+}
+
 void release(wsimg_plan* pl) {
     for (void* a : pl->allocations) (void)hipFree(a);
     pl->allocations.clear();
@@ -134,7 +141,7 @@ wsimg_status validate_params(const wsimg_params* p, int64_t max_vis) {
         return fail(WSIMG_E_INVALID, "n must be a power of two in [16, 16384]");
     if (p->n > 8192)
         return fail(WSIMG_E_UNSUPPORTED, "this build images n <= 8192");
-    if (p->n_wplanes < 1 || p->n_wplanes > 4096)
+    if (p->n_wplanes < 1 || p->n_wplanes > (int)kPlaneTab)
         return fail(WSIMG_E_INVALID, "n_wplanes must be in [1, 4096]");
     if (p->support < 3 || p->support > kMaxSupport || (p->support & 1) == 0 || p->support >= p->n)
         return fail(WSIMG_E_INVALID, "support must be odd, in [3, 15] and below n");
@@ -189,8 +196,12 @@ wsimg_status configure_shape(wsimg_plan* pl) {
     g.B = SH::B; g.log2B = Log2Of<SH::B>::value_any; g.NB = SH::N / SH::B;
     pl->nt1 = SH::NT1;
     pl->nt2 = SH::NT2;
+    pl->nt2a = SH::NT2A;
+    pl->bs = SH::BS;
     pl->lds1 = SH::LDS1_BYTES;
     pl->lds2 = SH::LDS2_BYTES;
+    pl->lds2s = SH::LDS2S_BYTES;
+    pl->lr2 = SH::LR2;
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, 7>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, kMaxSupport>,
@@ -200,9 +211,9 @@ wsimg_status configure_shape(wsimg_plan* pl) {
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_only<R, LOG2N, kMaxSupport>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2s));
     WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2s));
     WS_HIP(hipFuncSetAttribute((const void*)k_adj_cols<R, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
     const int lds_adj = (int)(SH::LDS1 * sizeof(typename Cx<R>::T));
@@ -248,13 +259,18 @@ template <typename R, int LOG2N>
 wsimg_status launch_cols(wsimg_plan* pl, int nch, void* image) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
+    static_assert(Shape<R, LOG2N>::E2 <= 16, "stacking strip flags hold 16 bits");
+    const int64_t nflags = (int64_t)nch * g.nw * (g.n >> pl->lr2);
+    hipLaunchKernelGGL(k_stack_flags, dim3(blocks_for(nflags, 256)), dim3(256), 0, pl->stream, g, nch, pl->lr2,
+                       (const uint8_t*)pl->occ, pl->sflags);
+    WS_LAUNCH_CHECK("stack_flags");
     if (g.crop > 0)
-        hipLaunchKernelGGL((k_cols_stack<R, LOG2N, true>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2),
-                           pl->lds2, pl->stream, g, pl->scalars, pl->occ, pl->plane_occ, (const C*)pl->inter,
+        hipLaunchKernelGGL((k_cols_stack<R, LOG2N, true>), dim3((unsigned)(g.n_img / pl->bs), (unsigned)nch), dim3(pl->nt2),
+                           pl->lds2s, pl->stream, g, pl->scalars, pl->sflags, pl->plane_occ, (const C*)pl->inter,
                            (const C*)pl->tw, (const R*)pl->inv_taper, (R*)image);
     else
-        hipLaunchKernelGGL((k_cols_stack<R, LOG2N, false>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2),
-                           pl->lds2, pl->stream, g, pl->scalars, pl->occ, pl->plane_occ, (const C*)pl->inter,
+        hipLaunchKernelGGL((k_cols_stack<R, LOG2N, false>), dim3((unsigned)(g.n_img / pl->bs), (unsigned)nch), dim3(pl->nt2),
+                           pl->lds2s, pl->stream, g, pl->scalars, pl->sflags, pl->plane_occ, (const C*)pl->inter,
                            (const C*)pl->tw, (const R*)pl->inv_taper, (R*)image);
     WS_LAUNCH_CHECK("cols_stack");
     return WSIMG_OK;
@@ -302,7 +318,7 @@ template <typename R, int LOG2N>
 wsimg_status launch_predict(wsimg_plan* pl, int nch, const void* image, void* vis_out) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
-    hipLaunchKernelGGL((k_adj_cols<R, LOG2N>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2), pl->lds2,
+    hipLaunchKernelGGL((k_adj_cols<R, LOG2N>), dim3((unsigned)g.NB, (unsigned)nch), dim3(pl->nt2a), pl->lds2,
                        pl->stream, g, pl->scalars, pl->occ, pl->plane_occ, (const R*)image, (const C*)pl->tw,
                        (const R*)pl->inv_taper, (C*)pl->inter);
     WS_LAUNCH_CHECK("adj_cols");
@@ -393,10 +409,6 @@ struct Stamp {
         return WSIMG_OK;
     }
 };
-
-inline unsigned blocks_for(int64_t count, int threads) {
-    return (unsigned)((count + threads - 1) / threads);
-}
 
 // Stages shared by wsimg_image and wsimg_grid: counters, plane ranges, bucket sort.
 // vis == nullptr: the sort for a prediction (records carry positions and their input rows,
@@ -638,6 +650,7 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     ALLOC(split_acc, (size_t)kMaxSplit * pl->lds1, "split strip sums");
     ALLOC(split_done, sizeof(uint32_t) * kMaxSplit, "split strip counters");
     ALLOC(plane_occ, (size_t)g.nw * mc, "plane occupancy");
+    ALLOC(sflags, sizeof(uint16_t) * mc * g.nw * (size_t)(n >> pl->lr2), "stacking strip flags");
     ALLOC(key, sizeof(uint32_t) * mv, "keys");
     ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
     ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * mv, "record cells");
