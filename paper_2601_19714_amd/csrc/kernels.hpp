@@ -632,8 +632,20 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
 #ifndef WSIMG_F32_LR1
 #define WSIMG_F32_LR1 4
 #endif
+// float stacking: radix 16 from N = 4096 up (1.26 -> 1.18 ms on a 4096^2 image of 32 planes),
+// radix 8 below (1024^2: 1.92 ms against 2.18 ms for 64 channels of 16 planes)
 #ifndef WSIMG_F32_LR2
-#define WSIMG_F32_LR2 3
+#define WSIMG_F32_LR2 4
+#endif
+#ifndef WSIMG_F32_LR2_SMALL
+#define WSIMG_F32_LR2_SMALL 3
+#endif
+// base radix of the prediction's column pass (the stacking pass's transpose)
+#ifndef WSIMG_F32_LR2A
+#define WSIMG_F32_LR2A 3
+#endif
+#ifndef WSIMG_F64_LR2A
+#define WSIMG_F64_LR2A 3
 #endif
 #ifndef WSIMG_F64_LR1
 #define WSIMG_F64_LR1 4
@@ -658,8 +670,9 @@ static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
 #define WSIMG_F64_PX2 4096
 #endif
 // image columns per stacking block (0: all B columns of a layout block).  float: one, so that
-// a block is 512 threads for a 4096-point column and two blocks share a CU (their barriers
-// overlap); measured 1.44 -> 1.26 ms on a 4096^2 image of 32 planes
+// several blocks share a CU and one block's barriers overlap another's work (a 4096^2 image
+// of 32 planes: 1.44 -> 1.26 ms with radix-8 passes, 1.18 ms with radix 16: 256 threads per
+// block, two blocks per CU)
 #ifndef WSIMG_F32_BS
 #define WSIMG_F32_BS 1
 #endif
@@ -692,10 +705,12 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int N = 1 << LOG2N;
     // base radices (log2), at most log2(N) - 1 so that a transform has two passes or more
     static constexpr int LR1_0 = sizeof(R) == 4 ? WSIMG_F32_LR1 : WSIMG_F64_LR1;
-    static constexpr int LR2_0 = sizeof(R) == 4 ? WSIMG_F32_LR2 : WSIMG_F64_LR2;
+    static constexpr int LR2_0 = sizeof(R) == 4 ? (LOG2N >= 12 ? WSIMG_F32_LR2 : WSIMG_F32_LR2_SMALL) : WSIMG_F64_LR2;
     static constexpr int LR1 = LR1_0 < LOG2N ? LR1_0 : LOG2N - 1;
     static constexpr int LR2 = LR2_0 < LOG2N ? LR2_0 : LOG2N - 1;
     static constexpr int E1 = 1 << LR1, E2 = 1 << LR2;
+    static constexpr int LR2A_0 = sizeof(R) == 4 ? WSIMG_F32_LR2A : WSIMG_F64_LR2A;
+    static constexpr int LR2A = LR2A_0 < LOG2N ? LR2A_0 : LOG2N - 1;
     static constexpr int CAP1 = LOG2N >= 12 ? WSIMG_STRIP_CELLS : WSIMG_STRIP_CELLS_SMALL;
     // a row at least; at most 4, so that small images still have many strips in flight and
     // few register walks per strip (a 256^2 image: 1.18 ms with 16-row strips)
@@ -711,7 +726,7 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int BS = (BS0 <= 0 || BS0 > B) ? B : BS0;
     static_assert((BS & (BS - 1)) == 0, "stacking columns per block: a power of two");
     static constexpr int NT2 = (BS * N / E2) < 64 ? 64 : (BS * N / E2);   // stacking
-    static constexpr int NT2A = (B * N / E2) < 64 ? 64 : (B * N / E2);    // prediction column pass
+    static constexpr int NT2A = (B * N >> LR2A) < 64 ? 64 : (B * N >> LR2A);   // prediction column pass
     static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
     static constexpr size_t LDS1_BYTES = (size_t)LDS1 * sizeof(double2);   // float64 accumulation
     static constexpr int LDS2 = lds_padded_elems_c(B * N);                 // complex elements
@@ -1078,10 +1093,10 @@ __device__ __forceinline__ void pass2_data(const typename Cx<R>::T* __restrict__
     }
 }
 
-// Waves per SIMD the stacking kernel is compiled for (0: the compiler's choice).  float: 4,
-// which caps its registers at 128 so that two 512-thread blocks fit on a CU.
+// Waves per SIMD the stacking kernel is compiled for (0: the compiler's choice; 4 caps its
+// registers at 128, for two 512-thread blocks per CU with a radix-8 pass).
 #ifndef WSIMG_F32_COLS_WAVES_PER_EU
-#define WSIMG_F32_COLS_WAVES_PER_EU 4
+#define WSIMG_F32_COLS_WAVES_PER_EU 0
 #endif
 #ifndef WSIMG_F64_COLS_WAVES_PER_EU
 #define WSIMG_F64_COLS_WAVES_PER_EU 0
@@ -1301,7 +1316,7 @@ k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ o
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
     constexpr int n = SH::N, nmask = n - 1, hn = n >> 1;
-    constexpr int B = SH::B, NT = SH::NT2A, LOG2B = Log2Of<B>::value_any, LR = SH::LR2;
+    constexpr int B = SH::B, NT = SH::NT2A, LOG2B = Log2Of<B>::value_any, LR = SH::LR2A;
     constexpr int elems = B * n;
     constexpr int PER = (elems + NT - 1) / NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
