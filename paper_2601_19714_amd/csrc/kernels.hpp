@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(kSortThreads)
 k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
               const void* __restrict__ rec, uint32_t* __restrict__ rec_cell2, void* __restrict__ rec2) {
     __shared__ uint32_t hist[kOriginBins];
-    __shared__ uint32_t part[kSortThreads];
+    __shared__ uint32_t part[kSortThreads / 64];
     constexpr int PER = kOriginBins / kSortThreads;
     const size_t b = (size_t)blockIdx.y * g.nb1 + blockIdx.x;
     const uint32_t beg = offsets[b << kLogReplicas], end = offsets[(b + 1) << kLogReplicas];
@@ -599,19 +599,22 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
     for (uint32_t r = beg + t; r < end; r += kSortThreads)
         atomicAdd(&hist[raw_origin<R>(fetch_record<R>(rec_cell, rec, r), g.log2H)], 1u);
     __syncthreads();
-    // exclusive scan of the bins: thread t owns bins [t * PER, (t + 1) * PER)
+    // exclusive scan of the bins: thread t owns bins [t * PER, (t + 1) * PER); the thread sums
+    // are scanned within each wave by shuffles, then the wave totals are added across waves
     uint32_t v[PER], sum = 0;
 #pragma unroll
     for (int i = 0; i < PER; ++i) { v[i] = hist[t * PER + i]; sum += v[i]; }
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < kSortThreads; o <<= 1) {
-        const uint32_t x = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
+    const int lane = t & 63, wave = t >> 6;
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
     }
-    uint32_t run = t > 0 ? part[t - 1] : 0u;
+    if (lane == 63) part[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int w = 0; w < wave; ++w) run += part[w];
 #pragma unroll
     for (int i = 0; i < PER; ++i) { hist[t * PER + i] = run; run += v[i]; }
     __syncthreads();
@@ -763,6 +766,10 @@ template <typename R, int LOG2N> struct Shape {
 #ifndef WSIMG_GRID_BATCH
 #define WSIMG_GRID_BATCH 4
 #endif
+// 1: a run's sums restart through a multiply-add by 0 instead of per-lane zeroing
+#ifndef WSIMG_GRID_RUNFMA
+#define WSIMG_GRID_RUNFMA 1
+#endif
 #ifndef WSIMG_GRID_CHUNK_MAX
 #define WSIMG_GRID_CHUNK_MAX 32
 #endif
@@ -836,6 +843,31 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
 #pragma unroll
             for (int a = 0; a < WMAX; ++a) sum[rr][a] = make_double2(0.0, 0.0);
         int cq = -1, cp = 0;
+#if WSIMG_GRID_RUNFMA
+        // dirty: the sums hold a run not yet added to the strip.  A flush leaves the sums as
+        // they are; the next record that adds taps scales them by 0 (keep) in the same fused
+        // multiply-add, so no lane zeroes registers on its own.
+        bool dirty = false;
+        auto flush = [&]() {
+            if (!dirty) return;
+            dirty = false;
+#pragma unroll
+            for (int rr = 0; rr < RW; ++rr) {
+                const int b = rlo + rr - cp;
+                if ((unsigned)b < (unsigned)W) {
+                    const int lrow = (rlo + rr - row0) << LOG2N;
+#pragma unroll
+                    for (int a = 0; a < WMAX; ++a) {
+                        if (a < W) {
+                            double2* dst = &acc[lds_pad(lrow + ((cq + a + shift) & nmask))];
+                            atomicAdd(&dst->x, sum[rr][a].x);
+                            atomicAdd(&dst->y, sum[rr][a].y);
+                        }
+                    }
+                }
+            }
+        };
+#else
         // add the run's sums to the strip (rows of the walk that origin (cq, cp) reaches)
         auto flush = [&]() {
             if (cq < 0) return;
@@ -856,6 +888,7 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                 }
             }
         };
+#endif
         // one record: bucket tracking, run bookkeeping and its taps in this walk
         auto process = [&](const RawRec<R>& x, uint32_t r) {
             while (r >= bend) {
@@ -875,6 +908,25 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
 #pragma unroll
             for (int a = 0; a < WMAX; ++a)
                 if (a < W) gx[a] = kb_tap<R>(kbc, a, fr.x);
+#if WSIMG_GRID_RUNFMA
+            // every row of the walk, with zero weight on the rows the record does not reach
+            const double keep = dirty ? 1.0 : 0.0;
+            dirty = true;
+#pragma unroll
+            for (int rr = 0; rr < RW; ++rr) {
+                const int b = rlo + rr - p0;
+                const bool reach = (unsigned)b < (unsigned)W;
+                const R gy = reach ? kb_tap<R>(kbc, reach ? b : 0, fr.y) : (R)0;
+                const R vr = v.x * gy, vi = v.y * gy;
+#pragma unroll
+                for (int a = 0; a < WMAX; ++a) {
+                    if (a < W) {
+                        sum[rr][a].x = __builtin_fma(sum[rr][a].x, keep, (double)(vr * gx[a]));
+                        sum[rr][a].y = __builtin_fma(sum[rr][a].y, keep, (double)(vi * gx[a]));
+                    }
+                }
+            }
+#else
 #pragma unroll
             for (int rr = 0; rr < RW; ++rr) {
                 const int b = rlo + rr - p0;
@@ -890,6 +942,7 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                     }
                 }
             }
+#endif
         };
         // records are fetched WSIMG_GRID_BATCH at a time, so that several loads are in flight
         constexpr uint32_t KB = WSIMG_GRID_BATCH;
