@@ -102,6 +102,41 @@ def test_fixed_range_and_clamping(oracle_mod):
     _check(oracle_mod, img, ref, ds.n, 7, ds.beta, 1e-12, full=True)
 
 
+@pytest.mark.parametrize("n", [1024, 4096])
+def test_sparse_plane_occupancy(oracle_mod, n):
+    """Rows on three w levels with a fixed plane range of 9 planes: planes 0, 3 and 7 hold rows,
+    the others are empty and lie between them (the stacking pass steps over empty planes and
+    loads each plane's strip flags two occupied planes ahead).  n = 4096 takes the radix-16
+    stacking pass."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    import synth
+    rng = np.random.default_rng(40 + n)
+    m = 20000
+    ds = _random_ds(40 + n, m, n, 9, 7, "f64")
+    lam = synth.C_LIGHT / ds.freq_hz
+    ds.uvw_m[:, 2] = np.array([-400.0, -100.0, 300.0])[rng.integers(0, 3, m)] * lam
+    wr = (-450.0, 450.0)       # plane width 100 wavelengths: the levels land in planes 0, 3, 7
+    kw = dict(n=n, pixel_rad=ds.pixel_rad, n_wplanes=9, support=7, beta=ds.beta, w_range=wr)
+    img64 = ws.image(*_dev(ds, torch), ds.freq_hz, **kw).cpu().numpy()
+    d32 = ds.as_precision("f32")
+    img32 = ws.image(*_dev(d32, torch), ds.freq_hz, **kw).cpu().numpy()
+    prm = _prm(oracle_mod, ds, w_range=wr)
+    if n <= 1024:
+        ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, prm)
+        _check(oracle_mod, img64, ref, n, 7, ds.beta, 1e-12, full=True, tag="sparse planes f64")
+        _check(oracle_mod, img32, ref, n, 7, ds.beta, 1e-5, tag="sparse planes f32")
+    else:
+        _check(oracle_mod, img32, img64, n, 7, ds.beta, 1e-5, tag="sparse planes f32 vs gpu f64")
+        rows, cols = _sample_pixels(n, 12, 5)
+        ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, prm, pixels=(rows, cols))
+        scale = np.max(np.abs(img64))
+        e64 = np.max(np.abs(img64[np.ix_(rows, cols)] - ref)) / scale
+        e32 = np.max(np.abs(img32[np.ix_(rows, cols)] - ref)) / scale
+        print(f"sparse planes n={n} sampled vs oracle: f64 {e64:.3e} f32 {e32:.3e}")
+        assert e64 <= 1e-12 and e32 <= 1e-5
+
+
 def test_drops_counts_and_nonfinite(oracle_mod):
     torch = _torch()
     import paper_2601_19714_amd as ws
