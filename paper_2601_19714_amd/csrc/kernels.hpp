@@ -778,7 +778,7 @@ template <typename R, int LOG2N> struct Shape {
 #define WSIMG_GRID_RUNFMA 1
 #endif
 #ifndef WSIMG_GRID_CHUNK_MAX
-#define WSIMG_GRID_CHUNK_MAX 32
+#define WSIMG_GRID_CHUNK_MAX 16
 #endif
 constexpr uint32_t kChunkMax = WSIMG_GRID_CHUNK_MAX;
 
