@@ -627,11 +627,12 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
 // ---------------------------------------------------------------------------------------
 // Work-group shapes, fixed per (precision, image size).  Each FFT runs on a base radix
 // 2^LR (2^LR elements per thread between LDS exchanges); the base radix of each pass and
-// the stacking block size are build-time choices (WSIMG_<precision>_LR1/_LR2/_PX2), picked
+// the stacking block sizes are build-time choices (WSIMG_<precision>_LR1/_LR2/_PX2/_BS), picked
 // by measurement.
 //   pass 1: H grid rows per strip; the strip accumulates in float64 (16 B per cell) whatever
 //           the precision, so H * N <= 8192 cells; NT1 = H * N / 2^LR1 threads;
-//   pass 2: B image columns per block, B * N = PX2 pixels, NT2 = B * N / 2^LR2 threads.
+//   pass 2: the intermediate's column blocks hold B columns, B * N = PX2 pixels; a stacking
+//           block takes BS <= B of them with NT2 = BS * N / 2^LR2 threads.
 #ifndef WSIMG_F32_LR1
 #define WSIMG_F32_LR1 4
 #endif
@@ -1104,10 +1105,12 @@ k_grid_rows(Geom g, WorkList* __restrict__ wl, const uint32_t* __restrict__ list
 // ---------------------------------------------------------------------------------------
 // column FFTs, w-phase, stacking over planes, taper
 //
-// Work-group = one block of B image columns, E = 2^LR2 pixels per thread.  Per plane:
+// Work-group = one block of BS image columns (of a layout block of B), E = 2^LR2 pixels per
+// thread.  Per occupied plane:
 //   * the inputs of the first radix-E pass come straight from HBM into registers (thread
-//     tid = b * B + c takes column c at rows b + m N/E, so a wave reads 64 consecutive
-//     elements of the contiguous [n][B] block); rows of empty strips read as 0;
+//     tid = b * BS + c takes column c at rows b + m N/E of the plane's [n][B] layout block);
+//     rows of empty strips read as 0, by the thread's packed strip flags (k_stack_flags),
+//     which are loaded two occupied planes ahead;
 //   * the middle passes run in LDS, the last pass leaves its outputs in registers;
 //   * each output is multiplied by exp(+2 pi i w_k (n - 1)) and its real part summed over
 //     planes (Kahan-compensated in float, plain in double);
