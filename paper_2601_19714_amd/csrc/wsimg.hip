@@ -230,20 +230,31 @@ wsimg_status configure_shape(wsimg_plan* pl) {
         if (e_ != hipSuccess) return fail(WSIMG_E_HIP, std::string("launch ") + what + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// The records are put in origin order inside each bucket (k_origin_sort) for the float plan
+// only: in float64 the sort (36-byte records) costs more than the longer runs save (C2 float64
+// 5.79 -> 5.44 ms without it; float32 3.03 -> 3.00 ms with it), and its gridding reads the
+// records in bucket order.
+#ifndef WSIMG_F64_ORIGIN_SORT
+#define WSIMG_F64_ORIGIN_SORT 0
+#endif
+template <typename R> constexpr bool origin_sorted() { return sizeof(R) == 4 || WSIMG_F64_ORIGIN_SORT; }
+
 // WMAX: the support class the gridding registers are sized for (W <= 7, else W <= 15).
 template <typename R, int LOG2N, int WMAX>
 wsimg_status launch_grid_w(wsimg_plan* pl, int nch, bool fft, void* out) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
+    const uint32_t* rc = origin_sorted<R>() ? pl->rec_cell2 : pl->rec_cell;
+    const void* rr = origin_sorted<R>() ? pl->rec2 : pl->rec;
     if (fft) {
         hipLaunchKernelGGL((k_grid_rows<R, LOG2N, WMAX>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1),
                            pl->lds1, pl->stream, g, pl->worklist, pl->list, pl->list_aux, pl->list_cap,
-                           pl->offsets, pl->rec_cell2, (const void*)pl->rec2, (const R*)pl->kbc, (const C*)pl->tw,
+                           pl->offsets, rc, rr, (const R*)pl->kbc, (const C*)pl->tw,
                            (C*)out, pl->split_acc, pl->split_done);
     } else {
         hipLaunchKernelGGL((k_grid_only<R, LOG2N, WMAX>), dim3((unsigned)(g.nw * g.S), (unsigned)nch),
-                           dim3(pl->nt1), pl->lds1, pl->stream, g, pl->offsets, pl->occ, pl->rec_cell2,
-                           (const void*)pl->rec2, (const R*)pl->kbc, (C*)out);
+                           dim3(pl->nt1), pl->lds1, pl->stream, g, pl->offsets, pl->occ, rc,
+                           rr, (const R*)pl->kbc, (C*)out);
     }
     WS_LAUNCH_CHECK("grid_rows");
     return WSIMG_OK;
@@ -475,7 +486,7 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     }
     if (auto r = st.after(4)) return r;
 
-    if (M > 0 && !predict) {
+    if (M > 0 && !predict && origin_sorted<R>()) {
         hipLaunchKernelGGL((k_origin_sort<R>), dim3((unsigned)pl->nb, nch), dim3(kSortThreads), 0, s, g,
                            pl->offsets, pl->rec_cell, (const void*)pl->rec, pl->rec_cell2, pl->rec2);
         WS_LAUNCH_CHECK("origin_sort");
@@ -655,9 +666,10 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
     ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * mv, "record cells");
     ALLOC(rec, (f32 ? 16 : 32) * mv, "records");
-    ALLOC(rec_cell2, f32 ? 256 : sizeof(uint32_t) * mv, "record cells by origin");
+    const bool sorted2 = f32 || WSIMG_F64_ORIGIN_SORT;     // origin-ordered copies exist
+    ALLOC(rec_cell2, (f32 || !sorted2) ? 256 : sizeof(uint32_t) * mv, "record cells by origin");
     ALLOC(rec_idx, sizeof(uint32_t) * mv, "record rows");
-    ALLOC(rec2, (f32 ? 16 : 32) * mv, "records by origin");
+    ALLOC(rec2, sorted2 ? (f32 ? 16 : 32) * mv : 256, "records by origin");
     ALLOC(inter, pl->cbytes * cells * mc, "row-transformed planes");
     ALLOC(tw, pl->cbytes * n, "twiddles");
     ALLOC(inv_taper, pl->rbytes * n_img, "taper");
