@@ -204,7 +204,7 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
 }
 
 // Bucket counters are replicated kReplicas times, laid out [bucket][replica]; the rows of
-// row block b of a channel (256 rows) count in replica b mod kReplicas.  The rows of one hot
+// row block b of a channel (kKeyThreads rows) count in replica b mod kReplicas.  The rows of one hot
 // bucket (tens of thousands near the uv-plane centre) then spread their atomics over
 // kReplicas addresses instead of one, and the bucket's rows still end up contiguous after
 // the scan.  (Blocks of consecutive rows, not single rows: a bucket's records keep their
@@ -224,9 +224,23 @@ constexpr int kLogReplicas = 6;
 #ifndef WSIMG_KEY_WAVE_AGG
 #define WSIMG_KEY_WAVE_AGG 2
 #endif
+// rows per k_key block: the hash aggregation spans the block, and consecutive rows (one time
+// step's baselines) repeat keys more often over a longer span (C2: 0.77 distinct keys per row
+// over 256 rows, 0.51 over 1024)
+#ifndef WSIMG_KEY_THREADS
+#define WSIMG_KEY_THREADS 1024
+#endif
+constexpr int kKeyThreads = WSIMG_KEY_THREADS;
+static_assert(kKeyThreads == 256 || kKeyThreads == 512 || kKeyThreads == 1024, "k_key block size");
+
+// Replica of the bucket counters that row i of a channel counts in: its k_key block's index
+// mod kReplicas (k_key and k_scatter must agree on it).
+__device__ __forceinline__ uint32_t row_replica(int64_t i) {
+    return (uint32_t)((i / kKeyThreads) & (kReplicas - 1));
+}
 
 template <typename WT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kKeyThreads)
 k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom g,
       const Scalars* __restrict__ sc, uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
       uint32_t* __restrict__ counts) {
@@ -245,18 +259,19 @@ k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom 
             kk = (uint32_t)(c * g.nb1 + k * g.S + (p0 >> g.log2H));
         }
     }
-    const uint32_t rep = blockIdx.x & (kReplicas - 1);
+    const uint32_t rep = row_replica((int64_t)blockIdx.x * kKeyThreads);
 #if WSIMG_KEY_WAVE_AGG == 2
     // block-wide aggregation through an LDS hash table (open addressing, 2x the block's
     // rows, so a free slot always exists): each distinct key of the block takes one atomic
-    constexpr int kSlots = 512;
+    constexpr int kSlots = 2 * kKeyThreads;
+    constexpr int kSlotBits = kKeyThreads == 256 ? 9 : (kKeyThreads == 512 ? 10 : 11);
     constexpr uint32_t kEmpty = 0xFFFFFFFFu;
     __shared__ uint32_t hkey[kSlots], hcnt[kSlots], hbase[kSlots];
     for (int i = threadIdx.x; i < kSlots; i += blockDim.x) { hkey[i] = kEmpty; hcnt[i] = 0u; }
     __syncthreads();
     uint32_t slot = 0, local = 0;
     if (kk != kEmpty) {
-        slot = (kk * 2654435761u) >> 23;          // 9-bit multiplicative hash
+        slot = (kk * 2654435761u) >> (32 - kSlotBits);   // multiplicative hash
         while (true) {
             const uint32_t prev = atomicCAS(&hkey[slot], kEmpty, kk);
             if (prev == kEmpty || prev == kk) break;
@@ -479,7 +494,7 @@ k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __re
     if (kk == 0xFFFFFFFFu) return;
     const double wt = (double)wts[m];
     RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support, g.fold_w);
-    const uint32_t rep = blockIdx.x & (kReplicas - 1);     // the row block's replica (as in k_key)
+    const uint32_t rep = row_replica(m - r0);              // the row block's replica (as in k_key)
     const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + rep] + rank[m];
     const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
     // a prediction's records carry no W*V: their value slot holds (1, 0) for a folded row
