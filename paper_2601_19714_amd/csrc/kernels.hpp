@@ -479,8 +479,14 @@ __device__ __forceinline__ uint32_t frac_code(double f) {
 
 // vis may be null (prediction: the records carry positions only, W*V = 0); rec_idx, when not
 // null, receives each record's input row.
+// rows per k_scatter block: blocks of 1024 (like k_key's) write the records of a row block's
+// buckets from one work-group (C2 scatter 0.20 -> 0.18 ms, 64 channels of 1024^2 0.99 -> 0.80 ms)
+#ifndef WSIMG_SCATTER_THREADS
+#define WSIMG_SCATTER_THREADS 1024
+#endif
+constexpr int kScatterThreads = WSIMG_SCATTER_THREADS;
 template <typename R, typename WT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kScatterThreads)
 k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __restrict__ vis,
           const WT* __restrict__ wts, Geom g, const uint32_t* __restrict__ key,
           const uint32_t* __restrict__ rank, const uint32_t* __restrict__ offsets,

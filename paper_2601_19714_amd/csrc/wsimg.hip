@@ -479,7 +479,7 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     if (auto r = st.after(3)) return r;
 
     if (M > 0) {
-        hipLaunchKernelGGL((k_scatter<R, R>), dim3(blocks_for(M, 256), nch), dim3(256), 0, s, ch, uvw,
+        hipLaunchKernelGGL((k_scatter<R, R>), dim3(blocks_for(M, kScatterThreads), nch), dim3(kScatterThreads), 0, s, ch, uvw,
                            (const C*)vis, (const R*)wts, g, pl->key, pl->rank, pl->offsets,
                            pl->rec_cell, pl->rec, predict ? pl->rec_idx : nullptr);
         WS_LAUNCH_CHECK("scatter");
