@@ -37,6 +37,8 @@ def lib():
         L.oracle_dft.restype = None
         L.oracle_degrid.argtypes = [i64, i64, i64, p, p, p, p, p, p]
         L.oracle_degrid.restype = None
+        L.oracle_kb_eval.argtypes = [i64, p, i64, ctypes.c_double, p]
+        L.oracle_kb_eval.restype = None
         _lib = L
     return _lib
 

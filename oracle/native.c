@@ -8,9 +8,37 @@
  *   w-term), evaluated at a list of pixels.
  * oracle_degrid: the transpose of oracle_grid_accumulate: each visibility reads
  *   the W x W cells its taps cover, weighted by the same separable kernel.
+ * oracle_kb_eval: the Kaiser-Bessel kernel of the gridding step (Sec. 2, Jackson et al.
+ *   1991) at a list of offsets, with I0 by its power series.
  */
 #include <math.h>
 #include <stdint.h>
+
+/* I0(z) = sum_k (z^2/4)^k / (k!)^2: term_k = term_{k-1} * (z^2/4) / k^2, summed until a term
+   is at most 1e-17 of the running sum (the same series and stopping rule as oracle/kb.py). */
+static double i0_series(double z)
+{
+    const double q = 0.25 * z * z;
+    double term = 1.0, total = 1.0;
+    for (int k = 1; k <= 500; ++k) {
+        term = term * q / ((double)k * (double)k);
+        total = total + term;
+        if (term <= 1e-17 * total) break;
+    }
+    return total;
+}
+
+/* out[i] = G(t[i]) = I0(beta sqrt(1 - (2 t / W)^2)) / I0(beta) for |t| <= W/2, else 0. */
+void oracle_kb_eval(int64_t count, const double *t, int64_t support, double beta, double *out)
+{
+    const double norm = i0_series(beta);
+    for (int64_t i = 0; i < count; ++i) {
+        double s = 2.0 * t[i] / (double)support;
+        double a = 1.0 - s * s;
+        if (a < 0.0) a = 0.0;
+        out[i] = fabs(t[i]) <= 0.5 * (double)support ? i0_series(beta * sqrt(a)) / norm : 0.0;
+    }
+}
 
 /* grid[(p0+b)*n + q0+a] += wv * gx[a] * gy[b] for every visibility r in idx. */
 void oracle_grid_accumulate(int64_t n, int64_t support, int64_t count,

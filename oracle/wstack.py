@@ -211,12 +211,17 @@ def direction_cosines(n: int, pixel_rad: float, rows, cols):
 def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
                  pixels: Optional[Tuple[Sequence[int], Sequence[int]]] = None,
                  planes: Optional[Sequence[int]] = None, complex_out: bool = False,
-                 prepared: Optional[Prepared] = None, normalize: bool = True) -> np.ndarray:
+                 prepared: Optional[Prepared] = None, normalize: bool = True,
+                 threads: int = 1) -> np.ndarray:
     """Steps 1-8: the dirty image [N, N] (or [|I|, |J|] at pixels = (I, J)).
 
     ``planes`` restricts steps 5-7 to a subset of w-planes (the rest contribute
     nothing); the normalisation keeps the full sum of weights.  normalize=False leaves
     out the division by the sum of weights (the imaging operator itself).
+
+    ``threads`` > 1 runs steps 5-7 for groups of planes in that many threads (plane k in
+    group k mod threads) and adds the groups' sums in group order: the same per-plane
+    arithmetic, only the order in which the planes' terms are added differs.
     """
     n = prm.n
     pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
@@ -228,24 +233,40 @@ def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
     if pr.sum_w == 0.0 and normalize:
         return np.zeros(shape, dtype=np.complex128 if complex_out else np.float64)
     _, _, nm1 = direction_cosines(n, prm.pixel_rad, rows, cols)
-    S = np.zeros(shape, dtype=np.complex128)
-    plist = range(prm.n_wplanes) if planes is None else planes
-    for k in plist:
-        if not np.any(pr.keep & (pr.k == k)):
-            continue
-        g = grid_plane(pr, vis, weights, prm, k)
-        o = prm.crop
-        if pixels is None:
-            P = plane_transform(g)[o:o + n, o:o + n]
-        else:
-            sel = pr.keep & (pr.k == k)
-            lo, hi = int(pr.p0[sel].min()), int(pr.p0[sel].max()) + prm.support - 1
-            P = plane_transform(g, (rows + o, cols + o), grid_rows=np.arange(lo, hi + 1))
-        del g
-        wk = pr.w_lo + (k + 0.5) * pr.dw
-        cyc = wk * nm1
-        cyc = cyc - np.round(cyc)
-        S += P * np.exp(2j * math.pi * cyc)
+    plist = list(range(prm.n_wplanes) if planes is None else planes)
+
+    def stack(group):
+        """Steps 5-7 over the planes of one group: sum_k P_k exp(+2 pi i w_k (n - 1))."""
+        S = np.zeros(shape, dtype=np.complex128)
+        for k in group:
+            if not np.any(pr.keep & (pr.k == k)):
+                continue
+            g = grid_plane(pr, vis, weights, prm, k)
+            o = prm.crop
+            if pixels is None:
+                P = plane_transform(g)[o:o + n, o:o + n]
+            else:
+                sel = pr.keep & (pr.k == k)
+                lo, hi = int(pr.p0[sel].min()), int(pr.p0[sel].max()) + prm.support - 1
+                P = plane_transform(g, (rows + o, cols + o), grid_rows=np.arange(lo, hi + 1))
+            del g
+            wk = pr.w_lo + (k + 0.5) * pr.dw
+            cyc = wk * nm1
+            cyc = cyc - np.round(cyc)
+            S += P * np.exp(2j * math.pi * cyc)
+        return S
+
+    if threads <= 1 or len(plist) <= 1:
+        S = stack(plist)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        t = min(int(threads), len(plist))
+        groups = [plist[g::t] for g in range(t)]
+        with ThreadPoolExecutor(t) as ex:
+            parts = list(ex.map(stack, groups))
+        S = parts[0]
+        for q in parts[1:]:
+            S += q
     xi_j = (cols - n // 2) / prm.n_grid
     xi_i = (rows - n // 2) / prm.n_grid
     corr = np.outer(_kb.kb_taper(xi_i, prm.support, prm.beta), _kb.kb_taper(xi_j, prm.support, prm.beta))

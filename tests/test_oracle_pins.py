@@ -50,6 +50,17 @@ def test_i0_matches_library(oracle_mod):
     assert np.max(np.abs(got / sp_i0(z) - 1.0)) < 1e-14
 
 
+def test_kb_native_matches_numpy_series(oracle_mod):
+    """The kernel evaluated in the C helper equals the numpy series of the same formula."""
+    rng = np.random.default_rng(3)
+    for W in (3, 7, 9, 15):
+        t = rng.uniform(-W / 2 - 0.5, W / 2 + 0.5, 20000)
+        t[:3] = (-W / 2, 0.0, W / 2)
+        got = oracle_mod.kb.kb(t, W, 2.34 * W)
+        ref = oracle_mod.kb.kb_numpy(t, W, 2.34 * W)
+        assert np.max(np.abs(got - ref)) <= 1e-15
+
+
 def test_kb_shape(oracle_mod):
     kbm = oracle_mod.kb
     for W in (7, 9):
