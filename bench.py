@@ -3,9 +3,15 @@
 
 A step is one whole dirty image (all stages: bucket sort, gridding + row FFT, column
 FFT + w-phase + stacking + taper) of one synthetic visibility set already resident in HBM.
-The default workload is the MeerKAT-shaped single channel: 7 257 600 visibilities,
-4096^2 image, 32 w-planes, Kaiser-Bessel support 7, float32 path; the float64 path is
-timed on the same inputs and its rate and the float32/float64 speedup are reported too.
+The default workload is the largest single-GPU one, LOFAR-shaped: 2^26 visibilities from 60
+stations spread log-radially to 100 km, 150 MHz, 8192^2 image, 64 w-planes, Kaiser-Bessel
+support 9, float32 path; the float64 path is timed on the same inputs and its rate and the
+float32/float64 speedup are reported too.  --workload c2 selects the MeerKAT-shaped single
+channel (7 257 600 visibilities, 4096^2, 32 w-planes, support 7).
+
+Both benched images are compared with the float64 oracle (vs_oracle): over every pixel on
+the support-7 workloads, at 32 x 32 pixels spread over the central 512^2 crop on the
+LOFAR-shaped one (where the oracle's cost is its gridding of all rows).
 
 With --workload c4 a step is one call that images all 64 channels of the batched
 MeerKAT-shaped set (856-1712 MHz, 1024^2 images, 16 w-planes, 0-60 % random flagging per
@@ -19,8 +25,12 @@ Prints ONE JSON line.  Extra objects:
   roofline     : the dominant kernel's algorithmic bytes (or flops) per launch over its
                  average duration, from HIP events recorded on the plan's stream during
                  the timed steps, against the MI355X peak;
-  cpu_baseline : the FP64 oracle timed on a bounded sample of the same workload on the
-                 host cores (test infrastructure, run only here, rank 0, N = 1).
+  roofline_gridding : the gridding stage (prep, sort, gridding + row transform) against the
+                 HBM peak: input rows plus row-transformed occupied strips over its time;
+  cpu_baseline : the FP64 oracle timed on the same workload on the host cores (all the cores
+                 this process may use, at most 16), the whole image where that takes a few
+                 tens of seconds, else a stated sample of w-planes (test infrastructure, run
+                 only here, rank 0, N = 1).
 """
 
 from __future__ import annotations
@@ -187,30 +197,99 @@ def run_gpu_batch(chans, steps: int, warmup: int):
             "ms_per_step_graph": 1e3 * wall_graph / steps}
 
 
-def cpu_baseline(ds, n_sample_planes: int):
-    """The oracle on a stratified sample of w-planes, scaled to the whole workload:
-    vis/s = M / (T_prepare + (Nw / n_sample) * T_sampled_planes)."""
+def host_threads(cap: int = 16) -> int:
+    """Cores this process may run on (sched_getaffinity), at most cap: a GPU machine gives one
+    GPU's share of its cores to the job."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
+
+
+def _errs(a, ref):
+    import numpy as np
+    d = a.astype(np.float64) - ref
+    return {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "rel_peak": float(np.max(np.abs(d)) / np.max(np.abs(ref)))}
+
+
+def oracle_check(ds, images: dict):
+    """The benched images against the float64 oracle.  Support 7: every pixel (and the inner
+    half); support 9: 32 x 32 pixels spread over the central 512^2 crop.  Returns the errors
+    and, where the oracle made the whole image, its wall time (it doubles as cpu_baseline)."""
     import numpy as np
     import oracle
     d = ds.as_precision("f64")
-    prm = oracle.Params(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta)
+    prm = oracle.Params(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, **_oracle_variant())
+    th = host_threads()
+    out = {"threads": th}
+    t0 = time.perf_counter()
+    if d.support <= 7:
+        ref = oracle.wstack_image(d.uvw_m, d.vis, d.weights, d.freq_hz, prm, threads=th)
+        wall = time.perf_counter() - t0
+        q = slice(d.n // 4, 3 * d.n // 4)
+        for prec, img in images.items():
+            out[prec] = {"full_image": _errs(img, ref), "inner_half": _errs(img[q, q], ref[q, q])}
+        out["where"] = "every pixel"
+        out["oracle_whole_image_s"] = wall
+    else:
+        rng = np.random.default_rng(3)
+        lo = d.n // 2 - 256
+        rows = np.unique(np.concatenate([[d.n // 2], rng.choice(np.arange(lo, lo + 512), 31, replace=False)]))
+        cols = np.unique(np.concatenate([[d.n // 2], rng.choice(np.arange(lo, lo + 512), 31, replace=False)]))
+        ref = oracle.wstack_image(d.uvw_m, d.vis, d.weights, d.freq_hz, prm, pixels=(rows, cols), threads=th)
+        for prec, img in images.items():
+            out[prec] = {"crop_sampled": _errs(img[np.ix_(rows, cols)], ref)}
+        out["where"] = f"{rows.size} x {cols.size} pixels of the central 512^2 crop"
+        out["oracle_s"] = time.perf_counter() - t0
+    ok = True
+    for prec in images:
+        tol = 1e-5 if prec == "f32" else 1e-12
+        ok &= all(v <= tol for part in out[prec].values() for v in part.values())
+    out["within_tolerance"] = bool(ok)
+    return out
+
+
+def _oracle_variant():
+    v = {}
+    if VARIANT.get("fold_w"):
+        v["fold"] = True
+    if VARIANT.get("pad") == 2:
+        v["pad"] = 2
+    return v
+
+
+def cpu_baseline(ds, check=None):
+    """The oracle's imaging rate on the host cores: the whole-image time of the oracle check
+    when it made the whole image, else the oracle on every 4th w-plane (all rows of those
+    planes, whole image), scaled to all planes: M / (T_prepare + 4 T_sampled)."""
+    import oracle
+    th = host_threads()
+    d = ds.as_precision("f64")
+    if check is not None and "oracle_whole_image_s" in check:
+        wall = check["oracle_whole_image_s"]
+        return {"value": d.m / wall, "unit": "visibilities/s", "cores": check["threads"], "kind": "oracle",
+                "sample": (f"whole image, all {d.m} rows, every step of the FP64 oracle (C gridding loop, "
+                           f"numpy FFT, w-phase, stack, taper), w-planes in {check['threads']} threads: "
+                           f"{wall:.1f} s")}
+    prm = oracle.Params(d.n, d.pixel_rad, d.n_wplanes, d.support, d.beta, **_oracle_variant())
     t0 = time.perf_counter()
     pr = oracle.prepare(d.uvw_m, d.weights, d.freq_hz, prm)
     t_prep = time.perf_counter() - t0
-    step = max(1, d.n_wplanes // n_sample_planes)
-    planes = list(range(0, d.n_wplanes, step))[:n_sample_planes]
+    step = 4 if d.n_wplanes >= 8 else 1
+    planes = list(range(step // 2, d.n_wplanes, step))
     t0 = time.perf_counter()
-    oracle.wstack_image(d.uvw_m, d.vis, d.weights, d.freq_hz, prm, planes=planes, prepared=pr)
+    oracle.wstack_image(d.uvw_m, d.vis, d.weights, d.freq_hz, prm, planes=planes, prepared=pr, threads=th)
     t_planes = time.perf_counter() - t0
-    est = t_prep + (d.n_wplanes / len(planes)) * t_planes
+    import numpy as np
     m_sample = int(np.isin(pr.k[pr.keep], planes).sum())
-    return {
-        "value": d.m / est, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
-        "sample": (f"FP64 oracle (steps 1-3 on all {d.m} rows: {t_prep:.2f} s; steps 4-8 on w-planes "
-                   f"{planes} of {d.n_wplanes}, {m_sample} rows: {t_planes:.2f} s), whole-image time "
-                   f"estimated as prepare + {d.n_wplanes}/{len(planes)} x sampled planes = {est:.1f} s; "
-                   f"single-threaded numpy FFT and C gridding loop"),
-    }
+    est = t_prep + (d.n_wplanes / len(planes)) * t_planes
+    return {"value": d.m / est, "unit": "visibilities/s", "cores": min(th, len(planes)), "kind": "oracle",
+            "sample": (f"FP64 oracle, steps 1-3 on all {d.m} rows ({t_prep:.1f} s), steps 4-8 (whole image) "
+                       f"on {len(planes)} of {d.n_wplanes} w-planes (every {step}th; {m_sample} rows) in "
+                       f"{min(th, len(planes))} threads ({t_planes:.1f} s); whole-image time estimated as "
+                       f"prepare + {d.n_wplanes // len(planes)} x sampled = {est:.1f} s")}
 
 
 def read_pmc_traffic(kernel: str, workload: str, src_hash: str):
@@ -231,12 +310,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
+    ap.add_argument("--max-rows", type=int, default=None, help="a shorter track (first rows, time-major)")
+    ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 path")
     ap.add_argument("--fold", action="store_true", help="w-folding (accuracy variant)")
     ap.add_argument("--pad2", action="store_true", help="grid of twice the image side (accuracy variant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-planes", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -273,7 +353,7 @@ def main():
         bench_adjoint(args)
         return
     t0 = time.perf_counter()
-    ds = synth.make_config(cfg, device="cuda" if torch.cuda.is_available() else "cpu")
+    ds = synth.make_config(cfg, device="cuda" if torch.cuda.is_available() else "cpu", max_rows=args.max_rows)
     log(f"generated {ds.name}: M={ds.m} n={ds.n} nw={ds.n_wplanes} W={ds.support} "
         f"in {time.perf_counter() - t0:.1f}s")
 
@@ -311,6 +391,14 @@ def main():
         roof["ms_per_launch"] = per_call[dominant]
         roof["traffic"] = read_pmc_traffic(dominant, ds.name, src_hash)
         roof["algorithmic_bytes"] = traffic[dominant]
+    # the gridding stage (S1-S3 with the fused row transform): input rows in, occupied strips out
+    grid_stages = ("zero_counts", "reduce", "key", "scan", "scatter", "origin_sort", "grid_rows")
+    t_grid = sum(per_call[k] for k in grid_stages) / 1e3
+    grid_bytes = m * (24 + 8 + 4) + st["n_strips_occupied"] * r32["info"]["strip_rows"] * ds.n * 8
+    roof_grid = {"bound": "hbm", "achieved": grid_bytes / t_grid / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": grid_bytes / t_grid / 1e9 / HBM_PEAK_GBS, "stages": list(grid_stages),
+                 "ms": t_grid * 1e3, "algorithmic_bytes": grid_bytes,
+                 "bytes_rule": "36 B per input row (uvw, vis, weight) + 8 B per cell of the occupied strips"}
 
     res = {
         "metric": METRIC, "value": value, "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps,
@@ -324,22 +412,28 @@ def main():
                       "strips_total": ds.n_wplanes * ds.n // r32["info"]["strip_rows"],
                       "strip_rows": r32["info"]["strip_rows"], "planes_occupied": nw_occ},
         "roofline": roof,
+        "roofline_gridding": roof_grid,
         "kernel_source_hash": src_hash,
     }
+    images = {"f32": r32["image"]}
     if r64 is not None:
         res["f64_value"] = m / (r64["ms_per_step"] / 1e3)
         res["f64_ms_per_step"] = r64["ms_per_step"]
         res["speedup_f32_over_f64"] = r64["ms_per_step"] / r32["ms_per_step"]
+        res["f64_stage_ms"] = {k: v / max(1, r64["timing"]["calls"]) for k, v in r64["timing"]["ms"].items()}
         a, b = r32["image"].astype(np.float64), r64["image"]
-        res["f32_vs_f64_full_image"] = {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
-                                        "rel_peak": float(np.max(np.abs(a - b)) / np.max(np.abs(b)))}
+        res["f32_vs_f64_full_image"] = _errs(a, b)
         c = slice(ds.n // 2 - 256, ds.n // 2 + 256)
-        res["f32_vs_f64_central_512"] = {
-            "rel_l2": float(np.linalg.norm(a[c, c] - b[c, c]) / np.linalg.norm(b[c, c])),
-            "rel_peak": float(np.max(np.abs(a[c, c] - b[c, c])) / np.max(np.abs(b[c, c])))}
+        res["f32_vs_f64_central_512"] = _errs(a[c, c], b[c, c])
+        images["f64"] = r64["image"]
+    check = None
+    if not args.no_oracle_check:
+        log(f"checking the benched images against the FP64 oracle on {host_threads()} threads ...")
+        check = oracle_check(ds, images)
+        res["vs_oracle"] = check
     if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on a sample of planes ...")
-        res["cpu_baseline"] = cpu_baseline(ds, args.cpu_sample_planes)
+        log("timing the FP64 oracle ...")
+        res["cpu_baseline"] = cpu_baseline(ds, check)
     print(json.dumps(res), flush=True)
 
 
@@ -462,7 +556,7 @@ def bench_batch(args):
     }
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample of one channel's planes ...")
-        cb = cpu_baseline(chans[0], args.cpu_sample_planes)
+        cb = cpu_baseline(chans[0])
         cb["sample"] = "channel 0 only (its per-visibility rate stands for every channel): " + cb["sample"]
         res["cpu_baseline"] = cb
     print(json.dumps(res), flush=True)

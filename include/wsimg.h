@@ -103,12 +103,22 @@ typedef struct {
 typedef struct {
     int32_t n, n_wplanes, support, precision;
     int32_t strip_rows;      /* grid rows per gridding work-group                          */
-    int32_t col_block;       /* image columns per stacking work-group                      */
-    int64_t n_buckets;       /* sort buckets: n_wplanes * n / strip_rows                   */
+    int32_t col_block;       /* image columns per block of the row-transformed planes     */
+    int64_t n_buckets;       /* sort buckets: n_wplanes * n_grid / strip_rows              */
     int64_t max_vis;
-    int64_t device_bytes;    /* device memory the plan holds                               */
+    int64_t device_bytes;    /* device memory the plan holds (or would hold)               */
     int64_t max_channels;    /* channels one wsimg_image_batch call may image              */
     int64_t n_grid;          /* grid side: n, or 2n with WSIMG_PAD2                        */
+    int32_t grid_threads;    /* threads of a gridding (+ row transform) work-group         */
+    int32_t stack_threads;   /* threads of a stacking (column transform) work-group        */
+    int32_t stack_cols;      /* image columns per stacking work-group                      */
+    int32_t stack_radix;     /* base radix of the stacking pass's column transform         */
+    int64_t lds_grid_bytes;  /* dynamic LDS of a gridding work-group                       */
+    int64_t lds_stack_bytes; /* dynamic LDS of a stacking work-group                       */
+    int64_t record_bytes;    /* bytes of one sorted visibility record                      */
+    int64_t row_capacity;    /* entries of each row-indexed scratch buffer: max_vis plus a
+                                slack, so a read one entry past the last row stays inside  */
+    int64_t list_capacity;   /* entries of the gridding work list                          */
 } wsimg_plan_info;
 
 #define WSIMG_N_KERNELS 8
@@ -156,6 +166,18 @@ wsimg_status wsimg_plan_set_stream(wsimg_plan *plan, void *hip_stream);
 
 /* Geometry and memory of a plan. */
 wsimg_status wsimg_plan_get_info(const wsimg_plan *plan, wsimg_plan_info *info);
+
+/*
+ * What wsimg_plan_create_batch(p, max_vis, max_channels) would build, without building it:
+ * the same checks of the parameters, then the geometry, work-group shapes and the device
+ * bytes the plan would hold (every scratch allocation summed), in *info.  Host arithmetic
+ * only: no HIP call, no GPU needed, nothing allocated; a caller can size its memory budget
+ * (or pick max_vis / max_channels to fit it) before creating a plan.
+ * Errors: as wsimg_plan_create_batch apart from WSIMG_E_NOMEM and WSIMG_E_HIP;
+ *         WSIMG_E_INVALID when info is NULL.
+ */
+wsimg_status wsimg_plan_query(const wsimg_params *p, int64_t max_vis, int32_t max_channels,
+                              wsimg_plan_info *info);
 
 /*
  * The dirty image (Sec. 2: Eqs. 1-3 and the phase shift and reduction of w-planes):

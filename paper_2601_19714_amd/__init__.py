@@ -14,7 +14,7 @@ from typing import Optional, Tuple
 
 from . import _lib
 
-__all__ = ["WsimgError", "Plan", "image", "grid", "predict", "stage_names", "version", "ImagingOperator"]
+__all__ = ["WsimgError", "Plan", "image", "grid", "predict", "query", "stage_names", "version", "ImagingOperator"]
 
 
 class WsimgError(RuntimeError):
@@ -39,6 +39,40 @@ def stage_names():
     return [L.wsimg_stage_name(i).decode() for i in range(_lib.WSIMG_N_KERNELS)]
 
 
+def _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad):
+    p = _lib.Params()
+    p.n, p.n_wplanes, p.support = int(n), int(n_wplanes), int(support)
+    p.precision = _prec_code(precision)
+    p.pixel_rad = float(pixel_rad)
+    p.beta = 0.0 if beta is None else float(beta)
+    p.flags = 0
+    if w_range is not None:
+        p.w_lo, p.w_hi = float(w_range[0]), float(w_range[1])
+        p.flags |= _lib.WSIMG_FIXED_WRANGE
+    if not normalize:
+        p.flags |= _lib.WSIMG_UNNORMALIZED
+    if fold_w:
+        p.flags |= _lib.WSIMG_FOLD_W
+    if pad not in (1, 2):
+        raise ValueError("pad must be 1 or 2")
+    if pad == 2:
+        p.flags |= _lib.WSIMG_PAD2
+    return p
+
+
+def query(n: int, pixel_rad: float, n_wplanes: int, support: int = 7, beta: Optional[float] = None,
+          precision: str = "f32", max_vis: int = 0, max_channels: int = 1,
+          w_range: Optional[Tuple[float, float]] = None, normalize: bool = True, fold_w: bool = False,
+          pad: int = 1) -> dict:
+    """What a Plan of these arguments would hold (wsimg_plan_query): shapes and device bytes,
+    computed on the host without a GPU."""
+    L = _lib.load()
+    p = _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad)
+    i = _lib.PlanInfo()
+    _check(L.wsimg_plan_query(ctypes.byref(p), int(max_vis), int(max_channels), ctypes.byref(i)))
+    return {f: getattr(i, f) for f, _ in _lib.PlanInfo._fields_}
+
+
 def _prec_code(precision: str) -> int:
     if precision in ("f32", "float32"):
         return _lib.WSIMG_F32
@@ -61,23 +95,7 @@ class Plan:
                                    else torch.device(device).index or 0)
         self.precision = "f32" if _prec_code(precision) == _lib.WSIMG_F32 else "f64"
         self.n, self.n_wplanes, self.support = int(n), int(n_wplanes), int(support)
-        p = _lib.Params()
-        p.n, p.n_wplanes, p.support = self.n, self.n_wplanes, self.support
-        p.precision = _prec_code(precision)
-        p.pixel_rad = float(pixel_rad)
-        p.beta = 0.0 if beta is None else float(beta)
-        p.flags = 0
-        if w_range is not None:
-            p.w_lo, p.w_hi = float(w_range[0]), float(w_range[1])
-            p.flags |= _lib.WSIMG_FIXED_WRANGE
-        if not normalize:
-            p.flags |= _lib.WSIMG_UNNORMALIZED
-        if fold_w:
-            p.flags |= _lib.WSIMG_FOLD_W
-        if pad not in (1, 2):
-            raise ValueError("pad must be 1 or 2")
-        if pad == 2:
-            p.flags |= _lib.WSIMG_PAD2
+        p = _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad)
         self.pad = int(pad)
         self._L = _lib.load()
         self._h = ctypes.c_void_p()

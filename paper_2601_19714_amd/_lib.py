@@ -26,7 +26,7 @@ WSIMG_N_KERNELS = 8
 # every symbol include/wsimg.h declares
 EXPORTS = (
     "wsimg_plan_create", "wsimg_plan_create_batch", "wsimg_plan_destroy", "wsimg_plan_set_stream",
-    "wsimg_plan_get_info", "wsimg_image", "wsimg_image_batch", "wsimg_predict", "wsimg_grid", "wsimg_set_timing", "wsimg_read_timing", "wsimg_stage_name",
+    "wsimg_plan_get_info", "wsimg_plan_query", "wsimg_image", "wsimg_image_batch", "wsimg_predict", "wsimg_grid", "wsimg_set_timing", "wsimg_read_timing", "wsimg_stage_name",
     "wsimg_status_string", "wsimg_last_error", "wsimg_version",
 )
 
@@ -48,7 +48,12 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("strip_rows", ctypes.c_int32), ("col_block", ctypes.c_int32),
                 ("n_buckets", ctypes.c_int64), ("max_vis", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("max_channels", ctypes.c_int64), ("n_grid", ctypes.c_int64)]
+                ("max_channels", ctypes.c_int64), ("n_grid", ctypes.c_int64),
+                ("grid_threads", ctypes.c_int32), ("stack_threads", ctypes.c_int32),
+                ("stack_cols", ctypes.c_int32), ("stack_radix", ctypes.c_int32),
+                ("lds_grid_bytes", ctypes.c_int64), ("lds_stack_bytes", ctypes.c_int64),
+                ("record_bytes", ctypes.c_int64), ("row_capacity", ctypes.c_int64),
+                ("list_capacity", ctypes.c_int64)]
 
 
 class Timing(ctypes.Structure):
@@ -76,6 +81,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.wsimg_plan_destroy.argtypes = [vp]
     L.wsimg_plan_set_stream.argtypes = [vp, vp]
     L.wsimg_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.wsimg_plan_query.argtypes = [ctypes.POINTER(Params), i64, i32, ctypes.POINTER(PlanInfo)]
     for f in (L.wsimg_image, L.wsimg_grid):
         f.argtypes = [vp, i64, vp, vp, vp, dbl, vp, ctypes.POINTER(Stats)]
     L.wsimg_image_batch.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, ctypes.POINTER(dbl), vp,
@@ -84,7 +90,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.wsimg_set_timing.argtypes = [vp, i32]
     L.wsimg_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     for f in (L.wsimg_plan_create, L.wsimg_plan_create_batch, L.wsimg_plan_destroy, L.wsimg_plan_set_stream,
-              L.wsimg_plan_get_info, L.wsimg_image, L.wsimg_image_batch, L.wsimg_predict, L.wsimg_grid,
+              L.wsimg_plan_get_info, L.wsimg_plan_query, L.wsimg_image, L.wsimg_image_batch, L.wsimg_predict, L.wsimg_grid,
               L.wsimg_set_timing,
               L.wsimg_read_timing):
         f.restype = ctypes.c_int

@@ -186,65 +186,6 @@ __device__ __forceinline__ void stockham_range(C* lds, const C* __restrict__ tw)
     }
 }
 
-// One Stockham pass from LDS buffer src to another buffer dst: each thread reads, transforms
-// and writes its butterflies with no barrier in between (the buffers differ), and one barrier
-// follows the writes.
-template <int RAD, int LOG2N, int LOG2L, int ROWS, int NT, typename C>
-__device__ __forceinline__ void stockham_pass_oop(const C* src, C* dst, const C* __restrict__ tw) {
-    constexpr int LOGR = Log2Of<RAD>::value;
-    constexpr int LSUB = LOG2N - LOGR;
-    constexpr int NBF = ROWS << LSUB;
-    constexpr int BPT = (NBF + NT - 1) / NT;
-    constexpr int L = 1 << LOG2L;
-    constexpr int TWSHIFT = LOG2N - LOG2L - LOGR;
-    const int tid = threadIdx.x;
-    C x[BPT][RAD];
-#pragma unroll
-    for (int t = 0; t < BPT; ++t) {
-        const int g = tid + t * NT;
-        if (NBF % NT == 0 || g < NBF) {
-            const int r = g >> LSUB, b = g & ((1 << LSUB) - 1);
-            const int base = (r << LOG2N) + b;
-#pragma unroll
-            for (int m = 0; m < RAD; ++m) x[t][m] = src[lds_pad(base + (m << LSUB))];
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < BPT; ++t) {
-        const int g = tid + t * NT;
-        if (NBF % NT == 0 || g < NBF) {
-            const int r = g >> LSUB, b = g & ((1 << LSUB) - 1);
-            const int k = b & (L - 1), j = b >> LOG2L;
-            if constexpr (L > 1) twiddle_inputs<RAD, TWSHIFT>(x[t], tw, k);
-            dft_small<RAD>(x[t]);
-            const int obase = (r << LOG2N) + (j << (LOG2L + LOGR)) + k;
-#pragma unroll
-            for (int m = 0; m < RAD; ++m) dst[lds_pad(obase + (m << LOG2L))] = x[t][m];
-        }
-    }
-    __syncthreads();
-}
-
-// Number of passes stockham_range runs from sub-length 2^LOG2L up to 2^STOP.
-template <int LOG2N, int LOGR, int LOG2L, int STOP> struct RangePasses {
-    static constexpr int REM = LOG2N % LOGR;
-    static constexpr int LR = (REM != 0 && LOG2L == LOGR) ? REM : LOGR;
-    static constexpr int value = LOG2L < STOP ? 1 + RangePasses<LOG2N, LOGR, (LOG2L < STOP ? LOG2L + LR : STOP), STOP>::value : 0;
-};
-template <int LOG2N, int LOGR, int STOP> struct RangePasses<LOG2N, LOGR, STOP, STOP> { static constexpr int value = 0; };
-
-// The passes of stockham_range, out of place: the first reads a and writes b, the next reads
-// b and writes a, and so on; the result is in b after an odd number of passes, else in a.
-template <int LOG2N, int LOGR, int LOG2L, int STOP, int ROWS, int NT, typename C>
-__device__ __forceinline__ void stockham_range_pp(C* a, C* b, const C* __restrict__ tw) {
-    if constexpr (LOG2L < STOP) {
-        constexpr int REM = LOG2N % LOGR;
-        constexpr int LR = (REM != 0 && LOG2L == LOGR) ? REM : LOGR;
-        stockham_pass_oop<(1 << LR), LOG2N, LOG2L, ROWS, NT>(a, b, tw);
-        stockham_range_pp<LOG2N, LOGR, LOG2L + LR, STOP, ROWS, NT>(b, a, tw);
-    }
-}
-
 // Full in-place transform of ROWS rows held in LDS (LOG2N > LOGR).
 template <int LOG2N, int LOGR, int ROWS, int NT, typename C>
 __device__ __forceinline__ void fft_rows_lds(C* lds, const C* __restrict__ tw) {

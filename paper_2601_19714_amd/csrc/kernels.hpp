@@ -213,17 +213,10 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
 constexpr int kReplicas = 64;
 constexpr int kLogReplicas = 6;
 
-// Ranks inside a (bucket, replica) counter.  WSIMG_KEY_WAVE_AGG selects how:
-//  2 (default): the block's rows group their keys in an LDS hash table; one global atomic per
-//     distinct key of the block, and each row's rank is that atomic's return plus its order
-//     in the table slot (C2 key stage 0.38 -> 0.30 ms, 64 channels of 1024^2 2.1 -> 1.1 ms);
-//  1: the lanes of a wave sharing a key elect a leader (a loop over the wave's distinct keys
-//     with scalar lane reads and ballots), and the leaders' atomics go out together;
-//  0: one atomic per row (the lanes hitting a hot bucket serialise in the cache: 3.4x slower
-//     than 1 on 64 channels of 1024^2, where most lanes of a wave share a few buckets).
-#ifndef WSIMG_KEY_WAVE_AGG
-#define WSIMG_KEY_WAVE_AGG 2
-#endif
+// Ranks inside a (bucket, replica) counter: the block's rows group their keys in an LDS hash
+// table; one global atomic per distinct key of the block, and each row's rank is that atomic's
+// return plus its order in the table slot (one atomic per row serialises the lanes that hit a
+// hot bucket; a per-wave leader loop was slower on many small channels).
 // rows per k_key block: the hash aggregation spans the block, and consecutive rows (one time
 // step's baselines) repeat keys more often over a longer span (C2: 0.77 distinct keys per row
 // over 256 rows, 0.51 over 1024)
@@ -260,7 +253,6 @@ k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom 
         }
     }
     const uint32_t rep = row_replica((int64_t)blockIdx.x * kKeyThreads);
-#if WSIMG_KEY_WAVE_AGG == 2
     // block-wide aggregation through an LDS hash table (open addressing, 2x the block's
     // rows, so a free slot always exists): each distinct key of the block takes one atomic
     constexpr int kSlots = 2 * kKeyThreads;
@@ -286,30 +278,6 @@ k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom 
     }
     __syncthreads();
     const uint32_t rr = kk != kEmpty ? hbase[slot] + local : 0u;
-#elif WSIMG_KEY_WAVE_AGG
-    const int lane = threadIdx.x & 63;
-    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    unsigned long long todo = __ballot(kk != 0xFFFFFFFFu);
-    uint32_t rr = 0, group = 0;
-    int my_leader = lane;
-    while (todo) {
-        const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)todo) - 1);
-        const uint32_t lkey = (uint32_t)__builtin_amdgcn_readlane((int)kk, leader);
-        const unsigned long long same = __ballot(kk == lkey);
-        if (kk == lkey) {
-            my_leader = leader;
-            rr = (uint32_t)__popcll(same & below);
-        }
-        if (lane == leader) group = (uint32_t)__popcll(same);
-        todo &= ~same;
-    }
-    uint32_t base = 0;
-    if (group) base = atomicAdd(&counts[((size_t)kk << kLogReplicas) + rep], group);
-    rr += __shfl(base, my_leader, 64);
-#else
-    uint32_t rr = 0;
-    if (kk != 0xFFFFFFFFu) rr = atomicAdd(&counts[((size_t)kk << kLogReplicas) + rep], 1u);
-#endif
     if (in) {
         key[m] = kk;
         rank[m] = rr;
@@ -714,20 +682,6 @@ static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
 #ifndef WSIMG_COLS_XCD_MAP
 #define WSIMG_COLS_XCD_MAP 1
 #endif
-// 1: the stacking pass runs its FFT passes out of place between two LDS buffers (one barrier
-// per pass instead of two, and none at the end of a plane), where both buffers fit
-#ifndef WSIMG_COLS_PINGPONG
-#define WSIMG_COLS_PINGPONG 0
-#endif
-// 1: the stacking pass keeps the per-pixel n - 1 values in registers, not in LDS
-#ifndef WSIMG_COLS_NM1_REGS
-#define WSIMG_COLS_NM1_REGS 0
-#endif
-// 1: the stacking pass re-reads its twiddles every plane instead of keeping them in
-// registers across planes (measured: keeping them is faster at every size timed)
-#ifndef WSIMG_COLS_TW_OPAQUE
-#define WSIMG_COLS_TW_OPAQUE 0
-#endif
 
 // bytes of the stacking pass's LDS plane-flag table: the largest plane count a plan takes
 constexpr size_t kPlaneTab = 4096;
@@ -765,13 +719,10 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr size_t LDS2_BYTES = (size_t)LDS2 * 2 * sizeof(R);      // column pass of prediction
     static constexpr int LDS2S = lds_padded_elems_c(BS * N);               // stacking FFT buffer
     static constexpr size_t LDS2S_BUF = (size_t)LDS2S * 2 * sizeof(R);
-    // stacking: two FFT buffers when out-of-place passes are on and both fit
-    static constexpr int NBUF2 = (WSIMG_COLS_PINGPONG && 2 * LDS2S_BUF <= 160 * 1024) ? 2 : 1;
-    // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer(s) and the
-    // plane flags (kPlaneTab bytes, after everything else)
-    static constexpr bool NM1_LDS = !WSIMG_COLS_NM1_REGS &&
-        NBUF2 * LDS2S_BUF + sizeof(double) * E2 * NT2 + kPlaneTab <= 160 * 1024;
-    static constexpr size_t PTAB_OFF = NBUF2 * LDS2S_BUF + (NM1_LDS ? sizeof(double) * E2 * NT2 : 0);
+    // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer and the plane
+    // flags (kPlaneTab bytes, after everything else), else it stays in registers
+    static constexpr bool NM1_LDS = LDS2S_BUF + sizeof(double) * E2 * NT2 + kPlaneTab <= 160 * 1024;
+    static constexpr size_t PTAB_OFF = LDS2S_BUF + (NM1_LDS ? sizeof(double) * E2 * NT2 : 0);
     static constexpr size_t LDS2S_BYTES = PTAB_OFF + kPlaneTab;
 };
 
@@ -794,10 +745,6 @@ template <typename R, int LOG2N> struct Shape {
 // keep every lane busy and dense ones merge long runs.
 #ifndef WSIMG_GRID_BATCH
 #define WSIMG_GRID_BATCH 4
-#endif
-// 1: a run's sums restart through a multiply-add by 0 instead of per-lane zeroing
-#ifndef WSIMG_GRID_RUNFMA
-#define WSIMG_GRID_RUNFMA 1
 #endif
 #ifndef WSIMG_GRID_CHUNK_MAX
 #define WSIMG_GRID_CHUNK_MAX 16
@@ -872,7 +819,6 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
 #pragma unroll
             for (int a = 0; a < WMAX; ++a) sum[rr][a] = make_double2(0.0, 0.0);
         int cq = -1, cp = 0;
-#if WSIMG_GRID_RUNFMA
         // dirty: the sums hold a run not yet added to the strip.  A flush leaves the sums as
         // they are; the next record that adds taps scales them by 0 (keep) in the same fused
         // multiply-add, so no lane zeroes registers on its own.
@@ -896,28 +842,6 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                 }
             }
         };
-#else
-        // add the run's sums to the strip (rows of the walk that origin (cq, cp) reaches)
-        auto flush = [&]() {
-            if (cq < 0) return;
-#pragma unroll
-            for (int rr = 0; rr < RW; ++rr) {
-                const int b = rlo + rr - cp;
-                if ((unsigned)b < (unsigned)W) {
-                    const int lrow = (rlo + rr - row0) << LOG2N;
-#pragma unroll
-                    for (int a = 0; a < WMAX; ++a) {
-                        if (a < W) {
-                            double2* dst = &acc[lds_pad(lrow + ((cq + a + shift) & nmask))];
-                            atomicAdd(&dst->x, sum[rr][a].x);
-                            atomicAdd(&dst->y, sum[rr][a].y);
-                        }
-                        sum[rr][a] = make_double2(0.0, 0.0);
-                    }
-                }
-            }
-        };
-#endif
         // one record: bucket tracking, run bookkeeping and its taps in this walk
         auto process = [&](const RawRec<R>& x, uint32_t r) {
             while (r >= bend) {
@@ -937,7 +861,6 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
 #pragma unroll
             for (int a = 0; a < WMAX; ++a)
                 if (a < W) gx[a] = kb_tap<R>(kbc, a, fr.x);
-#if WSIMG_GRID_RUNFMA
             // every row of the walk, with zero weight on the rows the record does not reach
             const double keep = dirty ? 1.0 : 0.0;
             dirty = true;
@@ -955,23 +878,6 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                     }
                 }
             }
-#else
-#pragma unroll
-            for (int rr = 0; rr < RW; ++rr) {
-                const int b = rlo + rr - p0;
-                if ((unsigned)b < (unsigned)W) {
-                    const R gy = kb_tap<R>(kbc, b, fr.y);
-                    const R vr = v.x * gy, vi = v.y * gy;
-#pragma unroll
-                    for (int a = 0; a < WMAX; ++a) {
-                        if (a < W) {
-                            sum[rr][a].x += (double)(vr * gx[a]);
-                            sum[rr][a].y += (double)(vi * gx[a]);
-                        }
-                    }
-                }
-            }
-#endif
         };
         // records are fetched WSIMG_GRID_BATCH at a time, so that several loads are in flight
         constexpr uint32_t KB = WSIMG_GRID_BATCH;
@@ -1220,12 +1126,10 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
     constexpr int LR = SH::LR2, E = SH::E2;
     static_assert(LOG2N > LR, "image side must exceed the base radix");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr bool PP = SH::NBUF2 == 2;
     C* lds0 = reinterpret_cast<C*>(smem_raw);
-    C* lds1 = lds0 + (PP ? SH::LDS2S : 0);
-    // n - 1 of each output slot: in LDS after the FFT buffer(s) (nm1s[s * NT + tid]) when it
+    // n - 1 of each output slot: in LDS after the FFT buffer (nm1s[s * NT + tid]) when it
     // fits there, else in registers
-    double* nm1s = reinterpret_cast<double*>(lds0 + SH::NBUF2 * SH::LDS2S);
+    double* nm1s = reinterpret_cast<double*>(lds0 + SH::LDS2S);
     double nm1r[SH::NM1_LDS ? 1 : E];
     nm1r[0] = 0.0;
     const int jb = stack_block<B / BS>(blockIdx.x, gridDim.x), c = blockIdx.y;
@@ -1276,9 +1180,6 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
     const int j0 = jb << LOG2BS;
     const C* cblk = cin + (size_t)(j0 >> LOG2B) * B * n + (j0 & (B - 1));
 
-    // out-of-place passes: a plane's first pass writes buffer pp; the passes after it alternate
-    constexpr int NMID = RangePasses<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L>::value;
-    int pp = 0;
     // planes k (in x), kn (its data in pf, loaded one plane ahead) and kn2 (its strip flags
     // in fl, loaded two planes ahead)
     int k = next_plane(0);
@@ -1301,8 +1202,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
             }
         }
         // first pass: radix E with L = 1 (no twiddles), registers to LDS
-        C* la = pp ? lds1 : lds0;
-        C* lb = pp ? lds0 : lds1;
+        C* la = lds0;
         if (first_active) {
             dft_small<E>(x);
             const int col = tid % BS, b = tid / BS;
@@ -1311,17 +1211,8 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
             for (int m = 0; m < E; ++m) la[lds_pad(base + m)] = x[m];
         }
         __syncthreads();
-        const C* twk = WSIMG_COLS_TW_OPAQUE ? opaque_ptr(tw) : tw;
-        if constexpr (PP) {
-            // the last pass reads lb after an odd number of middle passes, else la; the next
-            // plane's first pass writes the other buffer (its last reads had a barrier since)
-            stockham_range_pp<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L, BS, NT>(la, lb, twk);
-            fft_last_to_regs<LOG2N, LR, BS, NT>((NMID & 1) ? lb : la, twk, x);
-            if constexpr ((NMID & 1) == 0) pp ^= 1;
-        } else {
-            stockham_range<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L, BS, NT>(la, twk);
-            fft_last_to_regs<LOG2N, LR, BS, NT>(la, twk, x);
-        }
+        stockham_range<LOG2N, LR, LR, FftPlan<LOG2N, LR>::LAST_L, BS, NT>(la, tw);
+        fft_last_to_regs<LOG2N, LR, BS, NT>(la, tw, x);
         double wk;
         {
 #pragma clang fp contract(off)
@@ -1356,7 +1247,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
                 fl = (first_active && kn2 < g.nw) ? sfl[(uint32_t)kn2 * nr + fb] : 0u;
             }
         }
-        if constexpr (!PP) __syncthreads();
+        __syncthreads();
         k = kn;
         kn = kn2;
     }

@@ -187,9 +187,9 @@ wsimg_status upload_tables(wsimg_plan* pl) {
     return WSIMG_OK;
 }
 
-// Fix the work-group shapes of a (precision, n) plan and raise the dynamic-LDS limits.
+// Fix the work-group shapes of a (precision, n) plan (host arithmetic only, no HIP call).
 template <typename R, int LOG2N>
-wsimg_status configure_shape(wsimg_plan* pl) {
+wsimg_status fill_shape(wsimg_plan* pl) {
     using SH = Shape<R, LOG2N>;
     Geom& g = pl->g;
     g.H = SH::H; g.log2H = Log2Of<SH::H>::value_any; g.S = SH::N / SH::H;
@@ -202,6 +202,13 @@ wsimg_status configure_shape(wsimg_plan* pl) {
     pl->lds2 = SH::LDS2_BYTES;
     pl->lds2s = SH::LDS2S_BYTES;
     pl->lr2 = SH::LR2;
+    return WSIMG_OK;
+}
+
+// Raise the dynamic-LDS limits of a (precision, n) plan's kernels to the plan's sizes.
+template <typename R, int LOG2N>
+wsimg_status set_lds_limits(wsimg_plan* pl) {
+    using SH = Shape<R, LOG2N>;
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, 7>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, kMaxSupport>,
@@ -234,10 +241,8 @@ wsimg_status configure_shape(wsimg_plan* pl) {
 // only: in float64 the sort (36-byte records) costs more than the longer runs save (C2 float64
 // 5.79 -> 5.44 ms without it; float32 3.03 -> 3.00 ms with it), and its gridding reads the
 // records in bucket order.
-#ifndef WSIMG_F64_ORIGIN_SORT
-#define WSIMG_F64_ORIGIN_SORT 0
-#endif
-template <typename R> constexpr bool origin_sorted() { return sizeof(R) == 4 || WSIMG_F64_ORIGIN_SORT; }
+template <typename R> constexpr bool origin_sorted() { return sizeof(R) == 4; }
+constexpr bool origin_sorted_plan(bool f32) { return f32; }
 
 // WMAX: the support class the gridding registers are sized for (W <= 7, else W <= 15).
 template <typename R, int LOG2N, int WMAX>
@@ -303,7 +308,8 @@ wsimg_status launch_cols(wsimg_plan* pl, int nch, void* image) {
         default: return fail(WSIMG_E_UNSUPPORTED, "image size outside 16..8192");             \
     }
 
-template <typename R> wsimg_status configure(wsimg_plan* pl) { WS_SIZE_DISPATCH(R, pl->g.log2n, configure_shape, pl) }
+template <typename R> wsimg_status shape_of(wsimg_plan* pl) { WS_SIZE_DISPATCH(R, pl->g.log2n, fill_shape, pl) }
+template <typename R> wsimg_status lds_limits(wsimg_plan* pl) { WS_SIZE_DISPATCH(R, pl->g.log2n, set_lds_limits, pl) }
 template <typename R> wsimg_status grid_rows(wsimg_plan* pl, int nch, bool fft, void* out) {
     WS_SIZE_DISPATCH(R, pl->g.log2n, launch_grid_rows, pl, nch, fft, out)
 }
@@ -583,22 +589,21 @@ wsimg_status dispatch_predict(wsimg_plan* pl, int64_t n_vis, const double* uvw, 
     return finish_call(pl, 1, stats, false);
 }
 
-wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, int max_channels,
-                    void* hip_stream) {
-    if (!out) return fail(WSIMG_E_INVALID, "out is NULL");
-    *out = nullptr;
+// Rows of slack after the last row in every row-indexed scratch buffer (keys, ranks, records,
+// record rows): a read one record past the last one stays inside the allocation.  (A buffer
+// of exactly 16 * max_vis bytes can end on an allocation-granule boundary, e.g. 32 MiB for
+// 2^21 float records, where one 16-byte record past its end is unmapped memory.)
+constexpr size_t kRowSlack = 256;
+
+// Geometry and work-group shapes of a plan from its parameters: host arithmetic only.
+wsimg_status plan_geometry(wsimg_plan* pl, const wsimg_params* p, int64_t max_vis, int max_channels) {
     if (auto r = validate_params(p, max_vis)) return r;
     if (max_channels < 1 || max_channels > kMaxChannels)
         return fail(WSIMG_E_INVALID, "max_channels must be in [1, 65535]");
-
-    wsimg_plan* pl = new (std::nothrow) wsimg_plan();
-    if (!pl) return fail(WSIMG_E_NOMEM, "host allocation of the plan failed");
     pl->p = *p;
     if (!(pl->p.beta > 0.0)) pl->p.beta = 2.34 * pl->p.support;
     pl->max_vis = max_vis;
     pl->max_channels = max_channels;
-    pl->stream = (hipStream_t)hip_stream;
-
     const bool f32 = p->precision == WSIMG_F32;
     pl->rbytes = f32 ? 4 : 8;
     pl->cbytes = 2 * pl->rbytes;
@@ -616,16 +621,97 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     g.unnormalized = (p->flags & WSIMG_UNNORMALIZED) ? 1 : 0;
     g.fold_w = (p->flags & WSIMG_FOLD_W) ? 1 : 0;
     g.w_lo_fixed = p->w_lo; g.w_hi_fixed = p->w_hi;
-    {
-        wsimg_status rs = f32 ? configure<float>(pl) : configure<double>(pl);
-        if (rs) { delete pl; return rs; }
-    }
+    if (auto r = f32 ? shape_of<float>(pl) : shape_of<double>(pl)) return r;
     pl->nb = (int64_t)g.nw * g.S;
     g.nb1 = (int)pl->nb;
     g.NB = n_img / g.B;             // stacking blocks cover the image's columns only
-    if (pl->nb * max_channels > kMaxBucketsTotal) {
-        delete pl;
+    if (pl->nb * max_channels > kMaxBucketsTotal)
         return fail(WSIMG_E_UNSUPPORTED, "max_channels x n_wplanes x strips exceeds 2^25 sort buckets");
+    pl->list_cap = (uint32_t)((size_t)pl->nb * max_channels + (size_t)kMaxSplit * kMaxParts);
+    return WSIMG_OK;
+}
+
+// Every device allocation of a plan, in order: f(address of the plan member, bytes, name).
+template <typename F>
+wsimg_status for_each_allocation(wsimg_plan* pl, F&& f) {
+    const Geom& g = pl->g;
+    const bool f32 = pl->p.precision == WSIMG_F32;
+    const size_t rows = (size_t)std::max<int64_t>(pl->max_vis, 1) + kRowSlack;
+    const size_t mc = (size_t)pl->max_channels;
+    const size_t cells = (size_t)g.nw * g.plane_elems;
+    const size_t nbt = (size_t)pl->nb * mc;
+    size_t nparts_alloc = 0;
+    for (int c = 1; c <= pl->max_channels; ++c) nparts_alloc = std::max(nparts_alloc, (size_t)c * parts_target(c));
+    const bool sorted2 = origin_sorted_plan(f32);     // origin-ordered copies exist
+    const size_t rec_bytes = f32 ? 16 : 32;
+    wsimg_status r = WSIMG_OK;
+#define WS_ALLOC(field, bytes, name) \
+    if (!r) r = f((void**)&pl->field, (size_t)(bytes), name);
+    WS_ALLOC(partials, sizeof(Partial) * nparts_alloc, "partials");
+    WS_ALLOC(scalars, sizeof(Scalars) * mc, "scalars");
+    WS_ALLOC(worklist, sizeof(WorkList), "work list counters");
+    WS_ALLOC(row_off, sizeof(int64_t) * (mc + 1), "channel row offsets");
+    WS_ALLOC(freq, sizeof(double) * mc, "channel frequencies");
+    WS_ALLOC(counts, sizeof(uint32_t) * nbt * kReplicas, "counts");
+    WS_ALLOC(offsets, sizeof(uint32_t) * (nbt * kReplicas + 1), "offsets");
+    WS_ALLOC(tile_sums, sizeof(uint32_t) * ((nbt * kReplicas + kScanTile - 1) / kScanTile), "scan tiles");
+    WS_ALLOC(occ, nbt, "occupancy");
+    WS_ALLOC(list, sizeof(uint32_t) * pl->list_cap, "strip work list");
+    WS_ALLOC(list_aux, sizeof(uint32_t) * pl->list_cap, "strip work list parts");
+    WS_ALLOC(split_acc, (size_t)kMaxSplit * pl->lds1, "split strip sums");
+    WS_ALLOC(split_done, sizeof(uint32_t) * kMaxSplit, "split strip counters");
+    WS_ALLOC(plane_occ, (size_t)g.nw * mc, "plane occupancy");
+    WS_ALLOC(sflags, sizeof(uint16_t) * mc * g.nw * (size_t)(g.n >> pl->lr2), "stacking strip flags");
+    WS_ALLOC(key, sizeof(uint32_t) * rows, "keys");
+    WS_ALLOC(rank, sizeof(uint32_t) * rows, "ranks");
+    WS_ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * rows, "record cells");
+    WS_ALLOC(rec, rec_bytes * rows, "records");
+    WS_ALLOC(rec_cell2, (f32 || !sorted2) ? 256 : sizeof(uint32_t) * rows, "record cells by origin");
+    WS_ALLOC(rec_idx, sizeof(uint32_t) * rows, "record rows");
+    WS_ALLOC(rec2, sorted2 ? rec_bytes * rows : 256, "records by origin");
+    WS_ALLOC(inter, pl->cbytes * cells * mc, "row-transformed planes");
+    WS_ALLOC(tw, pl->cbytes * g.n, "twiddles");
+    WS_ALLOC(inv_taper, pl->rbytes * g.n_img, "taper");
+    WS_ALLOC(kbc, pl->rbytes * (size_t)pl->p.support * 17, "kernel polynomials");
+#undef WS_ALLOC
+    return r;
+}
+
+void fill_info(const wsimg_plan* plan, wsimg_plan_info* info) {
+    info->n = plan->p.n;
+    info->n_wplanes = plan->p.n_wplanes;
+    info->support = plan->p.support;
+    info->precision = plan->p.precision;
+    info->strip_rows = plan->g.H;
+    info->col_block = plan->g.B;
+    info->n_buckets = plan->nb;
+    info->max_vis = plan->max_vis;
+    info->device_bytes = plan->device_bytes;
+    info->max_channels = plan->max_channels;
+    info->n_grid = plan->g.n;
+    info->grid_threads = plan->nt1;
+    info->stack_threads = plan->nt2;
+    info->stack_cols = plan->bs;
+    info->stack_radix = 1 << plan->lr2;
+    info->lds_grid_bytes = (int64_t)plan->lds1;
+    info->lds_stack_bytes = (int64_t)plan->lds2s;
+    info->record_bytes = plan->p.precision == WSIMG_F32 ? 16 : 32;
+    info->row_capacity = (int64_t)((size_t)std::max<int64_t>(plan->max_vis, 1) + kRowSlack);
+    info->list_capacity = (int64_t)plan->list_cap;
+}
+
+wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, int max_channels,
+                    void* hip_stream) {
+    if (!out) return fail(WSIMG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    wsimg_plan* pl = new (std::nothrow) wsimg_plan();
+    if (!pl) return fail(WSIMG_E_NOMEM, "host allocation of the plan failed");
+    if (auto r = plan_geometry(pl, p, max_vis, max_channels)) { delete pl; return r; }
+    pl->stream = (hipStream_t)hip_stream;
+    const bool f32 = p->precision == WSIMG_F32;
+    {
+        wsimg_status rs = f32 ? lds_limits<float>(pl) : lds_limits<double>(pl);
+        if (rs) { delete pl; return rs; }
     }
 
     hipError_t he = hipGetDevice(&pl->device);
@@ -636,45 +722,10 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     // as many strip work-groups as fit at once: one per CU while the LDS strip exceeds 80 KB
     pl->persist_blocks = cus * std::max(1, (int)((160 * 1024) / std::max<size_t>(pl->lds1, 1)));
 
-    wsimg_status r = WSIMG_OK;
-    const size_t mv = (size_t)std::max<int64_t>(max_vis, 1);
+    wsimg_status r = for_each_allocation(pl, [pl](void** field, size_t bytes, const char* name) {
+        return dev_alloc(pl, field, bytes, name);
+    });
     const size_t mc = (size_t)max_channels;
-    const size_t cells = (size_t)g.nw * g.plane_elems;
-    const size_t nbt = (size_t)pl->nb * mc;
-    size_t nparts_alloc = 0;
-    for (int c = 1; c <= max_channels; ++c) nparts_alloc = std::max(nparts_alloc, (size_t)c * parts_target(c));
-    void* tmp = nullptr;
-#define ALLOC(field, bytes, name)                                                  \
-    if (!r) { r = dev_alloc(pl, &tmp, (bytes), name); pl->field = (decltype(pl->field))tmp; }
-    ALLOC(partials, sizeof(Partial) * nparts_alloc, "partials");
-    ALLOC(scalars, sizeof(Scalars) * mc, "scalars");
-    ALLOC(worklist, sizeof(WorkList), "work list counters");
-    ALLOC(row_off, sizeof(int64_t) * (mc + 1), "channel row offsets");
-    ALLOC(freq, sizeof(double) * mc, "channel frequencies");
-    ALLOC(counts, sizeof(uint32_t) * nbt * kReplicas, "counts");
-    ALLOC(offsets, sizeof(uint32_t) * (nbt * kReplicas + 1), "offsets");
-    ALLOC(tile_sums, sizeof(uint32_t) * ((nbt * kReplicas + kScanTile - 1) / kScanTile), "scan tiles");
-    ALLOC(occ, nbt, "occupancy");
-    pl->list_cap = (uint32_t)(nbt + (size_t)kMaxSplit * kMaxParts);
-    ALLOC(list, sizeof(uint32_t) * pl->list_cap, "strip work list");
-    ALLOC(list_aux, sizeof(uint32_t) * pl->list_cap, "strip work list parts");
-    ALLOC(split_acc, (size_t)kMaxSplit * pl->lds1, "split strip sums");
-    ALLOC(split_done, sizeof(uint32_t) * kMaxSplit, "split strip counters");
-    ALLOC(plane_occ, (size_t)g.nw * mc, "plane occupancy");
-    ALLOC(sflags, sizeof(uint16_t) * mc * g.nw * (size_t)(n >> pl->lr2), "stacking strip flags");
-    ALLOC(key, sizeof(uint32_t) * mv, "keys");
-    ALLOC(rank, sizeof(uint32_t) * mv, "ranks");
-    ALLOC(rec_cell, f32 ? 256 : sizeof(uint32_t) * mv, "record cells");
-    ALLOC(rec, (f32 ? 16 : 32) * mv, "records");
-    const bool sorted2 = f32 || WSIMG_F64_ORIGIN_SORT;     // origin-ordered copies exist
-    ALLOC(rec_cell2, (f32 || !sorted2) ? 256 : sizeof(uint32_t) * mv, "record cells by origin");
-    ALLOC(rec_idx, sizeof(uint32_t) * mv, "record rows");
-    ALLOC(rec2, sorted2 ? (f32 ? 16 : 32) * mv : 256, "records by origin");
-    ALLOC(inter, pl->cbytes * cells * mc, "row-transformed planes");
-    ALLOC(tw, pl->cbytes * n, "twiddles");
-    ALLOC(inv_taper, pl->rbytes * n_img, "taper");
-    ALLOC(kbc, pl->rbytes * (size_t)p->support * 17, "kernel polynomials");
-#undef ALLOC
     if (!r) {
         const size_t tb = sizeof(int64_t) * (mc + 1) + sizeof(double) * mc;
         hipError_t e = hipHostMalloc(&pl->staging, tb, hipHostMallocDefault);
@@ -751,17 +802,21 @@ wsimg_status wsimg_plan_set_stream(wsimg_plan* plan, void* hip_stream) {
 
 wsimg_status wsimg_plan_get_info(const wsimg_plan* plan, wsimg_plan_info* info) {
     if (!plan || !info) return fail(WSIMG_E_INVALID, "plan or info is NULL");
-    info->n = plan->p.n;
-    info->n_wplanes = plan->p.n_wplanes;
-    info->support = plan->p.support;
-    info->precision = plan->p.precision;
-    info->strip_rows = plan->g.H;
-    info->col_block = plan->g.B;
-    info->n_buckets = plan->nb;
-    info->max_vis = plan->max_vis;
-    info->device_bytes = plan->device_bytes;
-    info->max_channels = plan->max_channels;
-    info->n_grid = plan->g.n;
+    fill_info(plan, info);
+    return WSIMG_OK;
+}
+
+wsimg_status wsimg_plan_query(const wsimg_params* p, int64_t max_vis, int32_t max_channels, wsimg_plan_info* info) {
+    if (!info) return fail(WSIMG_E_INVALID, "info is NULL");
+    wsimg_plan q;
+    if (auto r = plan_geometry(&q, p, max_vis, max_channels)) return r;
+    int64_t bytes = 0;
+    for_each_allocation(&q, [&bytes](void**, size_t b, const char*) {
+        bytes += (int64_t)(b == 0 ? 256 : b);
+        return WSIMG_OK;
+    });
+    q.device_bytes = bytes;
+    fill_info(&q, info);
     return WSIMG_OK;
 }
 

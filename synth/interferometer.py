@@ -263,10 +263,12 @@ def _sky(spec, rng, fov_rad, pixel_rad):
 
 
 def make_config(i: int, device: str = "cpu", max_rows: Optional[int] = None,
-                noise: bool = True) -> Dataset:
+                noise: bool = True, geometry_only: bool = False) -> Dataset:
     """Build workload ``i`` (1, 2, 3 or 5) exactly as seeded: default_rng(1000 + i).
 
     ``max_rows`` truncates the time-major rows (a shorter track of the same array).
+    ``geometry_only`` leaves the visibilities zero (uvw, weights and the imaging parameters
+    are the workload's own; the sky is still drawn, so nothing else changes).
     """
     if i == 4:
         raise ValueError("config 4 is multi-channel: use make_channels()")
@@ -289,8 +291,11 @@ def make_config(i: int, device: str = "cpu", max_rows: Optional[int] = None,
     n = spec["n"]
     src = _sky(spec, rng, n * pixel, pixel)
     sig = src["sigma"] if np.any(src["sigma"] > 0) else None
-    vis = predict_point_sources(uvw, spec["freq_hz"], src["l"], src["m"], src["flux"], sig, device)
-    if noise and spec["noise"] > 0:
+    if geometry_only:
+        vis = np.zeros(uvw.shape[0], dtype=np.complex128)
+    else:
+        vis = predict_point_sources(uvw, spec["freq_hz"], src["l"], src["m"], src["flux"], sig, device)
+    if noise and spec["noise"] > 0 and not geometry_only:
         nz = rng.standard_normal((uvw.shape[0], 2)) * spec["noise"]
         vis = vis + (nz[:, 0] + 1j * nz[:, 1])
     w = np.ones(uvw.shape[0])

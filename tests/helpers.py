@@ -68,3 +68,24 @@ def _random_ds(seed, m, n, nw, W, prec, frac=0.4, wscale=300.0, dl=None):
     wts = rng.uniform(0.2, 2.0, m)
     ds = synth.Dataset("random", uvw, vis, wts, freq, n, dl, nw, W, 2.34 * W)
     return ds.as_precision(prec)
+
+
+def host_threads(cap=16):
+    """Threads for oracle work on the host: the cores this process may run on, at most cap
+    (a GPU machine gives one GPU's share of its cores)."""
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
+
+
+def crop_pixels(n, side, k, seed):
+    """k x k pixel rows/cols spread over the central side x side crop (the centre included)."""
+    rng = np.random.default_rng(seed)
+    lo = n // 2 - side // 2
+    rows = np.sort(rng.choice(np.arange(lo, lo + side), k, replace=False))
+    cols = np.sort(rng.choice(np.arange(lo, lo + side), k, replace=False))
+    rows[0], cols[0] = n // 2, n // 2
+    return np.unique(rows), np.unique(cols)

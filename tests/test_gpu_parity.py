@@ -243,59 +243,58 @@ def _sample_pixels(n, k, seed):
 
 
 @pytest.mark.slow
-def test_c2_full_size(oracle_mod):
+@pytest.mark.timeout(900)
+def test_c2_full_image_vs_oracle(oracle_mod):
+    """The MeerKAT-shaped workload at full size (7 257 600 rows, 4096^2, 32 planes, W = 7):
+    the whole float32 and float64 images against the whole float64 oracle image (R17: at
+    W = 7 the image is compared over every pixel), plus untapered and inner-half checks."""
     torch = _torch()
     import paper_2601_19714_amd as ws
     import synth
+    from helpers import host_threads
     ds = synth.make_config(2, device="cuda")
-    args32 = _dev(ds, torch)
-    d64 = ds.as_precision("f64")
-    args64 = _dev(d64, torch)
-    kw = dict(n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta)
-    img32 = ws.image(*args32, ds.freq_hz, **kw).cpu().numpy()
-    img64 = ws.image(*args64, ds.freq_hz, **kw).cpu().numpy()
-    # the float32 path against the float64 path over every pixel (W = 7)
-    _check(oracle_mod, img32, img64, ds.n, ds.support, ds.beta, 1e-5, full=True, tag="c2 f32 vs gpu f64")
-    rows, cols = _sample_pixels(ds.n, 12, 2)
-    ref = oracle_mod.wstack_image(d64.uvw_m, d64.vis, d64.weights, d64.freq_hz, _prm(oracle_mod, d64),
-                                  pixels=(rows, cols))
-    scale = np.max(np.abs(img64))   # errors relative to the image peak
-    e64 = np.max(np.abs(img64[np.ix_(rows, cols)] - ref)) / scale
-    e32 = np.max(np.abs(img32[np.ix_(rows, cols)] - ref)) / scale
-    print(f"c2 sampled vs oracle: f64 {e64:.3e} f32 {e32:.3e}")
-    assert e64 <= 1e-12 and e32 <= 1e-5
-
-
-@pytest.mark.slow
-@pytest.mark.skip(reason="a GPU memory fault ended a run of this test after a change to the gridding "
-                         "loop (record prefetch) and the origin sort (records kept in registers); both "
-                         "changes are taken out, no cause was shown, so this case stays off the GPU until "
-                         "one is")
-def test_c3_geometry_full_grid(oracle_mod):
-    """The 8192^2, 64-plane, W = 9 geometry at a shortened track (2^21 rows): sampled pixels
-    against the oracle; whole image float32 against float64."""
-    torch = _torch()
-    import paper_2601_19714_amd as ws
-    import synth
-    ds = synth.make_config(3, device="cuda", max_rows=1 << 21)
     d64 = ds.as_precision("f64")
     kw = dict(n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta)
     img32 = ws.image(*_dev(ds, torch), ds.freq_hz, **kw).cpu().numpy()
     img64 = ws.image(*_dev(d64, torch), ds.freq_hz, **kw).cpu().numpy()
-    # float32 against float64: untapered everywhere, inner half, and the central 512^2 crop
+    th = host_threads()
+    print(f"c2 oracle on {th} threads", flush=True)
+    ref = oracle_mod.wstack_image(d64.uvw_m, d64.vis, d64.weights, d64.freq_hz, _prm(oracle_mod, d64),
+                                  threads=th)
+    _check(oracle_mod, img64, ref, ds.n, ds.support, ds.beta, 1e-12, full=True, tag="c2 f64 vs oracle")
+    _check(oracle_mod, img32, ref, ds.n, ds.support, ds.beta, 1e-5, full=True, tag="c2 f32 vs oracle")
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_c3_geometry_full_grid(oracle_mod):
+    """The 8192^2, 64-plane, W = 9 geometry at a shortened track (2^21 rows).  Float32 against
+    float64 on the GPU: untapered everywhere, inner half, and the central 512^2 crop (R17's
+    place for this workload); both against the oracle at 32 x 32 pixels spread over the crop."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    import synth
+    from helpers import crop_pixels, host_threads
+    print("c3 geometry: 2^21 rows, n=8192, nw=64, W=9", flush=True)
+    ds = synth.make_config(3, device="cuda", max_rows=1 << 21)
+    d64 = ds.as_precision("f64")
+    kw = dict(n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta)
+    print("c3 float32 image", flush=True)
+    img32 = ws.image(*_dev(ds, torch), ds.freq_hz, **kw).cpu().numpy()
+    print("c3 float64 image", flush=True)
+    img64 = ws.image(*_dev(d64, torch), ds.freq_hz, **kw).cpu().numpy()
     _check(oracle_mod, img32, img64, ds.n, ds.support, ds.beta, 1e-5, tag="c3 f32 vs gpu f64")
     crop = slice(ds.n // 2 - 256, ds.n // 2 + 256)
     l2, pk = _errs(img32[crop, crop], img64[crop, crop])
     print(f"c3 central 512^2 crop f32 vs f64: {l2:.3e} / {pk:.3e}")
     assert l2 <= 1e-5 and pk <= 1e-5
-    rows, cols = _sample_pixels(ds.n, 8, 3)
+    rows, cols = crop_pixels(ds.n, 512, 32, 3)
     ref = oracle_mod.wstack_image(d64.uvw_m, d64.vis, d64.weights, d64.freq_hz, _prm(oracle_mod, d64),
-                                  pixels=(rows, cols))
-    scale = np.max(np.abs(img64))
-    e64 = np.max(np.abs(img64[np.ix_(rows, cols)] - ref)) / scale
-    e32 = np.max(np.abs(img32[np.ix_(rows, cols)] - ref)) / scale
-    print(f"c3 sampled vs oracle: f64 {e64:.3e} f32 {e32:.3e}")
-    assert e64 <= 1e-12 and e32 <= 1e-5
+                                  pixels=(rows, cols), threads=host_threads())
+    e64 = _errs(img64[np.ix_(rows, cols)], ref)
+    e32 = _errs(img32[np.ix_(rows, cols)], ref)
+    print(f"c3 crop-sampled vs oracle: f64 {e64[0]:.3e}/{e64[1]:.3e} f32 {e32[0]:.3e}/{e32[1]:.3e}")
+    assert max(e64) <= 1e-12 and max(e32) <= 1e-5
 
 
 # ---------------------------------------------------------------------------------------
