@@ -5,7 +5,7 @@
  * of Sec. 2 of the paper: visibilities are sorted into grid strips, convolved
  * onto the nearest of Nw w-planes with a separable Kaiser-Bessel kernel (Eq. 3),
  * each plane is 2D Fourier transformed, multiplied by its w-term phase and the
- * planes are summed (Eq. 2, "phase shift and reduction of w-planes"), and the
+ * planes are summed (Eq. 2: a per-plane w-phase, then a sum over planes), and the
  * result is divided by the kernel's Fourier transform and by the sum of weights.
  *
  * Conventions (every entry point):
@@ -71,6 +71,12 @@ typedef enum {
                                      the taper division drops from C(0)^2/C(1/2)^2 to
                                      C(0)^2/C(1/4)^2 (about 6 for W = 7).  wsimg_grid then
                                      writes [n_wplanes][2n][2n]                          */
+#define WSIMG_COMPLEX_OUT 0x10u    /* wsimg_image / wsimg_image_batch write the complex image
+                                     S / (sum W * C(xi_j) C(xi_i)), interleaved (re, im) of
+                                     the plan's real type per pixel ([n][n][2]), instead of
+                                     its real part (the paper's dirty image is real, Sec. 4;
+                                     the imaginary part is the image of the anti-Hermitian
+                                     part of the data).  Not for wsimg_predict            */
 #define WSIMG_FOLD_W 0x4u         /* w-folding: a row with w < 0 is taken as its conjugate
                                      partner (-u, -v, -w, conj V) (equal for a real sky),
                                      so the planes span |w| only; the real image is the same
@@ -180,7 +186,7 @@ wsimg_status wsimg_plan_query(const wsimg_params *p, int64_t max_vis, int32_t ma
                               wsimg_plan_info *info);
 
 /*
- * The dirty image (Sec. 2: Eqs. 1-3 and the phase shift and reduction of w-planes):
+ * The dirty image (Sec. 2: Eqs. 1-3, then the per-plane w-phase and the sum over planes):
  *   D(i,j) = Re sum_k P_k(i,j) exp(+2 pi i w_k (n_ij - 1)) / (sum W * C(xi_j) C(xi_i))
  * where P_k is the 2D transform (exp(+2 pi i ...), phase centre at n/2) of plane k of the
  * Kaiser-Bessel grid, w_k the plane centre, n_ij = sqrt(1 - l^2 - m^2) and C the kernel's

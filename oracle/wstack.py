@@ -8,14 +8,14 @@ It follows the method of Sec. 2 of the paper in its own order:
   2. the W taps start at floor(x + 1/2) - (W-1)/2; a visibility whose taps leave
      the grid, or whose uvw or weight is not finite, is dropped;
   3. Nw uniform w-planes over [w_lo, w_hi] (Eq. 2's integration range), each
-     visibility going to the plane that holds it (the "closest w-plane" of Sec. 2):
+     visibility going to the plane that holds it (Sec. 2: the nearest w-plane):
      k = clamp(floor((w - w_lo) / dw), 0, Nw-1), plane centre w_k = w_lo + (k + 1/2) dw;
   4. the separable Kaiser-Bessel kernel G (oracle.kb);
   5. convolutional gridding, Eq. 3: grid_k[p0+b][q0+a] += W_m V_m G(q0+a-x) G(p0+b-y);
   6. each plane's 2D transform with the + sign of Eq. 2 and the phase centre at N/2:
      P_k(i,j) = sum_{p,q} grid_k[p][q] exp(+2 pi i [(q-N/2)(j-N/2) + (p-N/2)(i-N/2)] / N);
-  7. the w-correction and reduction of the planes ("phase shift and reduction of
-     w-planes", Sec. 2; the w-term sign of Eq. 2):
+  7. the w-correction and reduction of the planes (Sec. 2: each plane is phase-shifted, then
+     the planes are summed; the w-term sign of Eq. 2):
      S(i,j) = sum_k P_k(i,j) exp(+2 pi i w_k (n_ij - 1));
   8. division by the kernel's Fourier transform on both axes and by the sum of
      weights (natural weighting, Sec. 4.2.1): D = Re S / (sum W * C(xi_j) C(xi_i)),

@@ -14,7 +14,8 @@ from typing import Optional, Tuple
 
 from . import _lib
 
-__all__ = ["WsimgError", "Plan", "image", "grid", "predict", "query", "stage_names", "version", "ImagingOperator"]
+__all__ = ["WsimgError", "Plan", "image", "grid", "predict", "query", "stage_names", "version",
+           "ImagingOperator"]
 
 
 class WsimgError(RuntimeError):
@@ -39,7 +40,8 @@ def stage_names():
     return [L.wsimg_stage_name(i).decode() for i in range(_lib.WSIMG_N_KERNELS)]
 
 
-def _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad):
+def _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad,
+            complex_out=False):
     p = _lib.Params()
     p.n, p.n_wplanes, p.support = int(n), int(n_wplanes), int(support)
     p.precision = _prec_code(precision)
@@ -57,6 +59,8 @@ def _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normaliz
         raise ValueError("pad must be 1 or 2")
     if pad == 2:
         p.flags |= _lib.WSIMG_PAD2
+    if complex_out:
+        p.flags |= _lib.WSIMG_COMPLEX_OUT
     return p
 
 
@@ -87,7 +91,7 @@ class Plan:
     def __init__(self, n: int, pixel_rad: float, n_wplanes: int, support: int = 7,
                  beta: Optional[float] = None, precision: str = "f32", max_vis: int = 0,
                  w_range: Optional[Tuple[float, float]] = None, device=None, max_channels: int = 1,
-                 normalize: bool = True, fold_w: bool = False, pad: int = 1):
+                 normalize: bool = True, fold_w: bool = False, pad: int = 1, complex_out: bool = False):
         import torch
 
         self._torch = torch
@@ -95,8 +99,10 @@ class Plan:
                                    else torch.device(device).index or 0)
         self.precision = "f32" if _prec_code(precision) == _lib.WSIMG_F32 else "f64"
         self.n, self.n_wplanes, self.support = int(n), int(n_wplanes), int(support)
-        p = _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad)
+        p = _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad,
+                    complex_out)
         self.pad = int(pad)
+        self.complex_out = bool(complex_out)
         self._L = _lib.load()
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -110,6 +116,10 @@ class Plan:
     def _dtypes(self):
         t = self._torch
         return (t.complex64, t.float32) if self.precision == "f32" else (t.complex128, t.float64)
+
+    def _image_dtype(self):
+        cdt, rdt = self._dtypes()
+        return cdt if self.complex_out else rdt
 
     def _args(self, uvw, vis, weights):
         t = self._torch
@@ -146,19 +156,20 @@ class Plan:
 
     # -- the calls -------------------------------------------------------------------------
     def image(self, uvw, vis, weights, freq_hz: float, out=None, stats: bool = False):
-        """Dirty image [n, n] (wsimg_image).  With stats=True returns (image, stats dict)."""
-        _, rdt = self._dtypes()
+        """Dirty image [n, n] (wsimg_image): real, or complex for a plan made with
+        complex_out=True.  With stats=True returns (image, stats dict)."""
+        rdt = self._image_dtype()
         if out is None:
             out = self._torch.empty((self.n, self.n), dtype=rdt, device=self.device)
         elif out.dtype != rdt or out.shape != (self.n, self.n) or not out.is_contiguous() or out.device != self.device:
-            raise ValueError("out must be a contiguous [n, n] tensor of the plan's real dtype on its device")
+            raise ValueError(f"out must be a contiguous [n, n] {rdt} tensor on the plan's device")
         return self._run(self._L.wsimg_image, uvw, vis, weights, freq_hz, out, stats)
 
     def image_batch(self, uvw, vis, weights, row_counts, freqs_hz, out=None, stats: bool = False):
         """Dirty images [n_channels, n, n] of the channels laid out one after another in the
         inputs: channel c owns the next row_counts[c] rows and has frequency freqs_hz[c]
         (wsimg_image_batch).  With stats=True returns (images, [stats dict per channel])."""
-        _, rdt = self._dtypes()
+        rdt = self._image_dtype()
         counts = [int(x) for x in row_counts]
         freqs = [float(x) for x in freqs_hz]
         nch = len(counts)
@@ -171,7 +182,7 @@ class Plan:
         if out is None:
             out = self._torch.empty(shape, dtype=rdt, device=self.device)
         elif out.dtype != rdt or tuple(out.shape) != shape or not out.is_contiguous() or out.device != self.device:
-            raise ValueError("out must be a contiguous [n_channels, n, n] tensor of the plan's real dtype")
+            raise ValueError(f"out must be a contiguous [n_channels, n, n] {rdt} tensor")
         self._stream()
         c_counts = (ctypes.c_int64 * nch)(*counts)
         c_freqs = (ctypes.c_double * nch)(*freqs)
@@ -260,13 +271,14 @@ class Plan:
 
 def image(uvw, vis, weights, freq_hz: float, *, n: int, pixel_rad: float, n_wplanes: int,
           support: int = 7, beta: Optional[float] = None, precision: Optional[str] = None,
-          w_range=None, stats: bool = False):
-    """One-shot dirty image (creates and frees a plan)."""
+          w_range=None, stats: bool = False, complex_out: bool = False):
+    """One-shot dirty image (creates and frees a plan); complex_out=True returns the complex
+    image S / (sum W C C) instead of its real part."""
     import torch
     if precision is None:
         precision = "f64" if vis.dtype == torch.complex128 else "f32"
     with Plan(n, pixel_rad, n_wplanes, support, beta, precision, max_vis=uvw.shape[0],
-              w_range=w_range, device=uvw.device) as p:
+              w_range=w_range, device=uvw.device, complex_out=complex_out) as p:
         return p.image(uvw, vis, weights, freq_hz, stats=stats)
 
 

@@ -21,6 +21,7 @@ WSIMG_FIXED_WRANGE = 0x1
 WSIMG_UNNORMALIZED = 0x2
 WSIMG_FOLD_W = 0x4
 WSIMG_PAD2 = 0x8
+WSIMG_COMPLEX_OUT = 0x10
 WSIMG_N_KERNELS = 8
 
 # every symbol include/wsimg.h declares

@@ -1110,7 +1110,9 @@ template <int G> __device__ __forceinline__ int stack_block(int bid, int nblk) {
 }
 
 // PAD: the grid is padded (the image is its central crop); without it the crop logic folds away.
-template <typename R, int LOG2N, bool PAD>
+// CPLX: the image is complex, S / (sum W C(xi_i) C(xi_j)), interleaved (re, im) per pixel;
+// the imaginary part is stacked like the real part (Kahan-compensated in float).
+template <typename R, int LOG2N, bool PAD, bool CPLX>
 __global__ void __launch_bounds__((Shape<R, LOG2N>::NT2), (ColsWaves<R>::value))
 k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict__ sflags,
              const uint8_t* __restrict__ plane_occ, const typename Cx<R>::T* __restrict__ inter,
@@ -1146,13 +1148,20 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
     const size_t plane_elems = PAD ? g.plane_elems : ((size_t)1 << (2 * LOG2N));
     const typename Cx<R>::T* cin = inter + (size_t)c * g.nw * plane_elems;
 
-    // comp is the Kahan compensation (float only)
-    R acc[E], comp[sizeof(R) == 4 ? E : 1];
+    // comp is the Kahan compensation (float only); acci / compi the imaginary part (CPLX)
+    constexpr int EI = CPLX ? E : 1;
+    R acc[E], comp[sizeof(R) == 4 ? E : 1], acci[EI], compi[sizeof(R) == 4 ? EI : 1];
     comp[0] = (R)0;
+    acci[0] = (R)0;
+    compi[0] = (R)0;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         acc[s] = (R)0;
         if constexpr (sizeof(R) == 4) comp[s] = (R)0;
+        if constexpr (CPLX) {
+            acci[s] = (R)0;
+            if constexpr (sizeof(R) == 4) compi[s] = (R)0;
+        }
         int col, ip;
         double v = 0.0;
         if (last_slot<LOG2N, LR, BS, NT>(tid, s, col, ip)) {
@@ -1240,6 +1249,17 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
             } else {
                 acc[s] += val;
             }
+            if constexpr (CPLX) {
+                const R vim = x[s].x * sn + x[s].y * cs;
+                if constexpr (sizeof(R) == 4) {
+                    const R y = vim - compi[s];
+                    const R tt = acci[s] + y;
+                    compi[s] = (tt - acci[s]) - y;
+                    acci[s] = tt;
+                } else {
+                    acci[s] += vim;
+                }
+            }
         }
         if constexpr (!Pass2Prefetch<R>::value) {
             if (kn < g.nw) {
@@ -1259,9 +1279,17 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
         int col, ip;
         if (last_slot<LOG2N, LR, BS, NT>(tid, s, col, ip)) {
             const int i = ((ip + hn) & nmask) - crop, j = (jb << LOG2BS) + col;
-            if (!PAD || (i >= 0 && i < nimg))
-                image[(size_t)c * nimg * nimg + (size_t)i * nimg + j] =
-                    scale_ok ? acc[s] * inv_taper[i] * inv_taper[j] * inv_sw : (R)0;
+            if (!PAD || (i >= 0 && i < nimg)) {
+                const size_t o = (size_t)c * nimg * nimg + (size_t)i * nimg + j;
+                const R ti = inv_taper[i], tj = inv_taper[j];
+                const R re = scale_ok ? acc[s] * ti * tj * inv_sw : (R)0;
+                if constexpr (CPLX) {
+                    const R im = scale_ok ? acci[s] * ti * tj * inv_sw : (R)0;
+                    reinterpret_cast<C*>(image)[o] = cmake<C>(re, im);
+                } else {
+                    image[o] = re;
+                }
+            }
         }
     }
 }

@@ -152,7 +152,7 @@ wsimg_status validate_params(const wsimg_params* p, int64_t max_vis) {
         return fail(WSIMG_E_INVALID, "field too wide: a corner pixel has l^2 + m^2 >= 1");
     if (!std::isfinite(p->beta)) return fail(WSIMG_E_INVALID, "beta must be finite");
     if (p->reserved != 0 ||
-        (p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED | WSIMG_FOLD_W | WSIMG_PAD2)) != 0)
+        (p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED | WSIMG_FOLD_W | WSIMG_PAD2 | WSIMG_COMPLEX_OUT)) != 0)
         return fail(WSIMG_E_INVALID, "unknown flags or reserved field set");
     if ((p->flags & WSIMG_PAD2) && p->n > 4096)
         return fail(WSIMG_E_UNSUPPORTED, "a padded grid is at most 8192 cells: n <= 4096 with WSIMG_PAD2");
@@ -217,9 +217,13 @@ wsimg_status set_lds_limits(wsimg_plan* pl) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_only<R, LOG2N, kMaxSupport>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
-    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, false>,
+    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, false, false>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2s));
-    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, true>,
+    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, true, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2s));
+    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, false, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2s));
+    WS_HIP(hipFuncSetAttribute((const void*)k_cols_stack<R, LOG2N, true, true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2s));
     WS_HIP(hipFuncSetAttribute((const void*)k_adj_cols<R, LOG2N>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds2));
@@ -280,14 +284,20 @@ wsimg_status launch_cols(wsimg_plan* pl, int nch, void* image) {
     hipLaunchKernelGGL(k_stack_flags, dim3(blocks_for(nflags, 256)), dim3(256), 0, pl->stream, g, nch, pl->lr2,
                        (const uint8_t*)pl->occ, pl->sflags);
     WS_LAUNCH_CHECK("stack_flags");
-    if (g.crop > 0)
-        hipLaunchKernelGGL((k_cols_stack<R, LOG2N, true>), dim3((unsigned)(g.n_img / pl->bs), (unsigned)nch), dim3(pl->nt2),
-                           pl->lds2s, pl->stream, g, pl->scalars, pl->sflags, pl->plane_occ, (const C*)pl->inter,
-                           (const C*)pl->tw, (const R*)pl->inv_taper, (R*)image);
-    else
-        hipLaunchKernelGGL((k_cols_stack<R, LOG2N, false>), dim3((unsigned)(g.n_img / pl->bs), (unsigned)nch), dim3(pl->nt2),
-                           pl->lds2s, pl->stream, g, pl->scalars, pl->sflags, pl->plane_occ, (const C*)pl->inter,
-                           (const C*)pl->tw, (const R*)pl->inv_taper, (R*)image);
+    const dim3 grid((unsigned)(g.n_img / pl->bs), (unsigned)nch);
+    auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(pl->nt2), pl->lds2s, pl->stream, g, pl->scalars, pl->sflags,
+                           pl->plane_occ, (const C*)pl->inter, (const C*)pl->tw, (const R*)pl->inv_taper,
+                           (R*)image);
+    };
+    const bool cplx = (pl->p.flags & WSIMG_COMPLEX_OUT) != 0;
+    if (g.crop > 0) {
+        if (cplx) launch(k_cols_stack<R, LOG2N, true, true>);
+        else launch(k_cols_stack<R, LOG2N, true, false>);
+    } else {
+        if (cplx) launch(k_cols_stack<R, LOG2N, false, true>);
+        else launch(k_cols_stack<R, LOG2N, false, false>);
+    }
     WS_LAUNCH_CHECK("cols_stack");
     return WSIMG_OK;
 }
@@ -581,6 +591,8 @@ wsimg_status dispatch_predict(wsimg_plan* pl, int64_t n_vis, const double* uvw, 
     Batch bt;
     if (auto r = validate_call(pl, 1, &n_vis, &freq, uvw, wts, wts, vis_out, bt)) return r;
     if (!image) return fail(WSIMG_E_INVALID, "image pointer is NULL");
+    if (pl->p.flags & WSIMG_COMPLEX_OUT)
+        return fail(WSIMG_E_INVALID, "wsimg_predict takes a real image: the plan has WSIMG_COMPLEX_OUT");
     if (stats && capturing(pl)) return fail(WSIMG_E_INVALID, "stats need a host wait: not under graph capture");
     WS_HIP(hipSetDevice(pl->device));
     wsimg_status r = pl->p.precision == WSIMG_F32 ? run_predict<float>(pl, bt, uvw, wts, image, vis_out)

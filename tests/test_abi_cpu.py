@@ -60,7 +60,7 @@ def _params(mod, **kw):
     ("n", 100), ("n", 8), ("n", 32768), ("n_wplanes", 0), ("n_wplanes", 5000),
     ("support", 8), ("support", 1), ("support", 17), ("precision", 3),
     ("pixel_rad", 0.0), ("pixel_rad", float("nan")), ("pixel_rad", 0.01),
-    ("beta", float("inf")), ("reserved", 1), ("flags", 0x10),
+    ("beta", float("inf")), ("reserved", 1), ("flags", 0x20),
 ])
 def test_invalid_params_rejected_on_host(lib, field, value):
     L, mod = lib
@@ -70,6 +70,16 @@ def test_invalid_params_rejected_on_host(lib, field, value):
     assert st == mod.WSIMG_E_INVALID, (field, value, st)
     assert h.value is None
     assert L.wsimg_last_error()
+
+
+def test_every_declared_flag_is_accepted_on_host(lib):
+    """Each flag the header declares passes the host checks (plan_query: no GPU needed)."""
+    L, mod = lib
+    for flag in (mod.WSIMG_FIXED_WRANGE, mod.WSIMG_UNNORMALIZED, mod.WSIMG_FOLD_W, mod.WSIMG_PAD2,
+                 mod.WSIMG_COMPLEX_OUT):
+        p = _params(mod, flags=flag, w_lo=-1.0, w_hi=1.0)
+        info = mod.PlanInfo()
+        assert L.wsimg_plan_query(ctypes.byref(p), 100, 1, ctypes.byref(info)) == mod.WSIMG_OK, flag
 
 
 def test_fixed_range_and_capacity_rules(lib):

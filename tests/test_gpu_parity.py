@@ -297,6 +297,77 @@ def test_c3_geometry_full_grid(oracle_mod):
     assert max(e64) <= 1e-12 and max(e32) <= 1e-5
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_complex_out_c1(oracle_mod, c1, prec):
+    """WSIMG_COMPLEX_OUT (reading R10): the complex image S / (sum W C(xi_i) C(xi_j)) against
+    the oracle's complex image, both parts; its real part equals the real image.  The C1 sky
+    is real but its visibilities carry no Hermitian partners, so Im S is as large as Re S."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = c1.as_precision(prec)
+    kw = dict(n=ds.n, pixel_rad=ds.pixel_rad, n_wplanes=ds.n_wplanes, support=ds.support, beta=ds.beta)
+    img = ws.image(*_dev(ds, torch), ds.freq_hz, complex_out=True, **kw).cpu().numpy()
+    real = ws.image(*_dev(ds, torch), ds.freq_hz, **kw).cpu().numpy()
+    assert np.iscomplexobj(img) and img.shape == (ds.n, ds.n)
+    ref = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, _prm(oracle_mod, ds), complex_out=True)
+    assert np.linalg.norm(ref.imag) > 0.1 * np.linalg.norm(ref.real)
+    _check(oracle_mod, img, ref, ds.n, ds.support, ds.beta, TOL[prec], full=True, tag=f"complex c1 {prec}")
+    # the imaginary part alone is noise-like (no point-source peak), so like random data its
+    # full-image peak error in float32 is set by the corner amplification of the taper: full
+    # check in float64, untapered everywhere and inner half in both
+    _check(oracle_mod, img.imag, ref.imag, ds.n, ds.support, ds.beta, TOL[prec], full=(prec == "f64"),
+           tag=f"imag c1 {prec}")
+    assert max(_errs(img.real, real)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,nw,W,m,pad", [(64, 3, 15, 3000, 1), (512, 5, 7, 40000, 1), (256, 4, 9, 20000, 2)])
+def test_complex_out_shapes_and_batch(oracle_mod, prec, n, nw, W, m, pad):
+    """Complex images of other sizes, supports and the padded grid, one channel and two
+    channels in one batch call, against the oracle's complex images."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = _random_ds(900 + n + W, m, n, nw, W, prec)
+    d64 = ds.as_precision("f64")
+    half = m // 2
+    with ws.Plan(n, ds.pixel_rad, nw, W, ds.beta, prec, max_vis=ds.m, max_channels=2, pad=pad,
+                 complex_out=True) as p:
+        u, v, w = _dev(ds, torch)
+        one = p.image(u, v, w, ds.freq_hz).cpu().numpy()
+        two = p.image_batch(u, v, w, [half, m - half], [ds.freq_hz, 1.25 * ds.freq_hz]).cpu().numpy()
+    assert one.dtype == (np.complex64 if prec == "f32" else np.complex128)
+    prm = _prm(oracle_mod, d64)
+    prm.pad = pad
+    refs = [oracle_mod.wstack_image(d64.uvw_m, d64.vis, d64.weights, d64.freq_hz, prm, complex_out=True),
+            oracle_mod.wstack_image(d64.uvw_m[:half], d64.vis[:half], d64.weights[:half], d64.freq_hz, prm,
+                                    complex_out=True),
+            oracle_mod.wstack_image(d64.uvw_m[half:], d64.vis[half:], d64.weights[half:], 1.25 * d64.freq_hz,
+                                    prm, complex_out=True)]
+    tol = TOL[prec]
+    for tag, img, ref in (("one", one, refs[0]), ("ch0", two[0], refs[1]), ("ch1", two[1], refs[2])):
+        if pad == 2:
+            t = _taper_pad(oracle_mod, n, W, ds.beta)
+            tt = np.outer(t, t)
+            ua, fa = _errs(img * tt, ref * tt), _errs(img, ref)
+            print(f"complex pad2 {tag} {prec}: untapered {ua[0]:.2e}/{ua[1]:.2e} full {fa[0]:.2e}/{fa[1]:.2e}")
+            assert max(ua) <= tol and max(fa) <= tol
+        else:
+            _check(oracle_mod, img, ref, n, W, ds.beta, tol, full=(prec == "f64" and W <= 7),
+                   tag=f"complex {tag} {prec} n={n}")
+
+
+def test_complex_out_rejected_by_predict():
+    """A complex-output plan images only: its prediction call is an error, not a silent
+    reinterpretation of the image buffer."""
+    torch = _torch()
+    import paper_2601_19714_amd as ws
+    ds = _random_ds(5, 100, 64, 2, 7, "f32")
+    with ws.Plan(64, ds.pixel_rad, 2, 7, precision="f32", max_vis=ds.m, complex_out=True) as p:
+        u, _, w = _dev(ds, torch)
+        with pytest.raises(ws.WsimgError):
+            p.predict(u, w, ds.freq_hz, torch.zeros((64, 64), dtype=torch.float32, device=u.device))
+
+
 # ---------------------------------------------------------------------------------------
 # properties of the GPU path itself (any size)
 
