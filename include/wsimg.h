@@ -265,6 +265,33 @@ wsimg_status wsimg_grid(wsimg_plan *plan, int64_t n_vis, const double *uvw_m,
                         const void *vis, const void *weights, double freq_hz,
                         void *grid_out, wsimg_stats *stats);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): wsimg_image without a plan.  Every scratch buffer
+ * of the call (sort counters and records, the row-transformed planes, the tables) is carved
+ * from one static device array of WSIMG_NOALLOC_SCRATCH_BYTES that the library's code object
+ * holds on each GPU it runs on, from load to process end; the call makes no hipMalloc,
+ * hipFree or other allocating call.  The caller still passes the inputs and the output.
+ *  p        : parameters as for wsimg_plan_create (checked the same way).
+ *  n_vis .. image_out : as wsimg_image; hip_stream: the stream the work is enqueued on.
+ *  stats    : as wsimg_image (non-NULL waits for the stream).
+ * The scratch a call needs grows with n, n_wplanes and n_vis (wsimg_plan_query's
+ * device_bytes for max_vis = n_vis, plus alignment); a call that needs more than the array
+ * holds returns WSIMG_E_CAPACITY before any device work (host arithmetic only).  Heavy
+ * strips are not split across work-groups here (split-strip slots would have to stay zero
+ * between calls), so one very dense strip can make this call slower than wsimg_image.
+ * The kernel tables (twiddles, taper, kernel polynomials) are uploaded when the geometry
+ * differs from the previous call's on that device; that upload waits for the stream.
+ * All calls on one GPU share its array and the array keeps the last call's contents: calls
+ * that overlap on one GPU (two streams, or a call before the previous one's work has
+ * finished on another stream) race and give wrong images; host threads are serialised.
+ * Errors: as wsimg_image; WSIMG_E_CAPACITY also for a scratch need beyond the array.
+ */
+#define WSIMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+wsimg_status wsimg_image_noalloc(const wsimg_params *p, int64_t n_vis, const double *uvw_m,
+                                 const void *vis, const void *weights, double freq_hz,
+                                 void *image_out, void *hip_stream, wsimg_stats *stats);
+
 /* Per-stage device timing with HIP events on the plan's stream (enable != 0 turns it on and
  * clears the totals).  wsimg_read_timing waits for the stream and returns the totals. */
 wsimg_status wsimg_set_timing(wsimg_plan *plan, int32_t enable);

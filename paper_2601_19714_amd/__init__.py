@@ -14,7 +14,7 @@ from typing import Optional, Tuple
 
 from . import _lib
 
-__all__ = ["WsimgError", "Plan", "image", "grid", "predict", "query", "stage_names", "version",
+__all__ = ["WsimgError", "Plan", "image", "image_noalloc", "grid", "predict", "query", "stage_names", "version",
            "ImagingOperator"]
 
 
@@ -280,6 +280,39 @@ def image(uvw, vis, weights, freq_hz: float, *, n: int, pixel_rad: float, n_wpla
     with Plan(n, pixel_rad, n_wplanes, support, beta, precision, max_vis=uvw.shape[0],
               w_range=w_range, device=uvw.device, complex_out=complex_out) as p:
         return p.image(uvw, vis, weights, freq_hz, stats=stats)
+
+
+def image_noalloc(uvw, vis, weights, freq_hz: float, out, *, n: int, pixel_rad: float, n_wplanes: int,
+                  support: int = 7, beta: Optional[float] = None, w_range=None, stats: bool = False):
+    """Dirty image into the caller's `out` [n, n] through wsimg_image_noalloc: no plan and no
+    device allocation (the library's static scratch array holds every intermediate buffer);
+    precision from the vis dtype.  Raises WsimgError (WSIMG_E_CAPACITY) when the geometry and
+    row count need more than that array holds."""
+    import torch
+    precision = "f64" if vis.dtype == torch.complex128 else "f32"
+    cdt, rdt = (torch.complex64, torch.float32) if precision == "f32" else (torch.complex128, torch.float64)
+    m = int(uvw.shape[0]) if uvw.dim() == 2 else -1
+    if uvw.dtype != torch.float64 or uvw.dim() != 2 or uvw.shape[1] != 3:
+        raise ValueError("uvw must be a float64 tensor of shape [M, 3] (metres)")
+    if vis.dtype != cdt or vis.shape != (m,) or weights.dtype != rdt or weights.shape != (m,):
+        raise ValueError(f"vis must be {cdt} [M] and weights {rdt} [M]")
+    if out.dtype != rdt or tuple(out.shape) != (n, n):
+        raise ValueError(f"out must be {rdt} of shape [n, n]")
+    for name, x in (("uvw", uvw), ("vis", vis), ("weights", weights), ("out", out)):
+        if x.device != uvw.device or not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous on {uvw.device}")
+    L = _lib.load()
+    p = _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, True, False, 1)
+    st = _lib.Stats()
+    with torch.cuda.device(uvw.device):
+        stream = torch.cuda.current_stream(uvw.device).cuda_stream
+        _check(L.wsimg_image_noalloc(ctypes.byref(p), m, ctypes.c_void_p(uvw.data_ptr()),
+                                     ctypes.c_void_p(vis.data_ptr()), ctypes.c_void_p(weights.data_ptr()),
+                                     float(freq_hz), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream),
+                                     ctypes.byref(st) if stats else None))
+    if stats:
+        return out, {f: getattr(st, f) for f, _ in _lib.Stats._fields_}
+    return out
 
 
 def grid(uvw, vis, weights, freq_hz: float, *, n: int, pixel_rad: float, n_wplanes: int,

@@ -28,8 +28,9 @@ WSIMG_N_KERNELS = 8
 EXPORTS = (
     "wsimg_plan_create", "wsimg_plan_create_batch", "wsimg_plan_destroy", "wsimg_plan_set_stream",
     "wsimg_plan_get_info", "wsimg_plan_query", "wsimg_image", "wsimg_image_batch", "wsimg_predict", "wsimg_grid", "wsimg_set_timing", "wsimg_read_timing", "wsimg_stage_name",
-    "wsimg_status_string", "wsimg_last_error", "wsimg_version",
+    "wsimg_status_string", "wsimg_last_error", "wsimg_version", "wsimg_image_noalloc",
 )
+WSIMG_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Params(ctypes.Structure):
@@ -88,11 +89,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.wsimg_image_batch.argtypes = [vp, i32, ctypes.POINTER(i64), vp, vp, vp, ctypes.POINTER(dbl), vp,
                                     ctypes.POINTER(Stats)]
     L.wsimg_predict.argtypes = [vp, i64, vp, vp, dbl, vp, vp, ctypes.POINTER(Stats)]
+    L.wsimg_image_noalloc.argtypes = [ctypes.POINTER(Params), i64, vp, vp, vp, dbl, vp, vp, ctypes.POINTER(Stats)]
     L.wsimg_set_timing.argtypes = [vp, i32]
     L.wsimg_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     for f in (L.wsimg_plan_create, L.wsimg_plan_create_batch, L.wsimg_plan_destroy, L.wsimg_plan_set_stream,
               L.wsimg_plan_get_info, L.wsimg_plan_query, L.wsimg_image, L.wsimg_image_batch, L.wsimg_predict, L.wsimg_grid,
-              L.wsimg_set_timing,
+              L.wsimg_set_timing, L.wsimg_image_noalloc,
               L.wsimg_read_timing):
         f.restype = ctypes.c_int
     L.wsimg_stage_name.argtypes = [i32]

@@ -105,6 +105,17 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t v) 
         p[i] = v;
 }
 
+// The channel table of a one-channel call, written on the device from kernel arguments (the
+// allocation-free entry point has no pinned staging buffer).
+__global__ void k_set_channel(int64_t* __restrict__ row_off, double* __restrict__ freq, int64_t n_vis,
+                              double freq_hz) {
+    if (threadIdx.x == 0) {
+        row_off[0] = 0;
+        row_off[1] = n_vis;
+        freq[0] = freq_hz;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_reduce_sum(T v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -77,6 +78,10 @@ struct wsimg_plan {
     double2* split_acc = nullptr;  // float64 sums of split strips (zero between calls)
     uint32_t* split_done = nullptr;
     int persist_blocks = 256;      // work-groups of the persistent gridding kernel
+    // the allocation-free entry point's transient plans: the channel table is written by a
+    // kernel (no pinned staging), and no strip is split (no split-sum slots to keep zero)
+    bool direct_channels = false;
+    bool no_split = false;
     uint32_t *key = nullptr, *rank = nullptr, *rec_cell = nullptr, *rec_cell2 = nullptr;
     uint32_t* rec_idx = nullptr;   // input row of each record (prediction)
     void *rec = nullptr, *rec2 = nullptr, *inter = nullptr;   // records by bucket; by (bucket, origin)
@@ -398,6 +403,13 @@ bool capturing(const wsimg_plan* pl) {
 // rewritten only after the device has copied the previous call's table.  Under capture the
 // table goes to the graph's own buffer, with no host wait.
 wsimg_status upload_channels(wsimg_plan* pl, const Batch& bt) {
+    if (pl->direct_channels) {
+        if (bt.nch != 1) return fail(WSIMG_E_INVALID, "a direct channel table holds one channel");
+        hipLaunchKernelGGL(k_set_channel, dim3(1), dim3(64), 0, pl->stream, pl->row_off, pl->freq,
+                           bt.counts[0], bt.freqs[0]);
+        WS_LAUNCH_CHECK("set_channel");
+        return WSIMG_OK;
+    }
     const bool cap = capturing(pl);
     if (!cap && pl->staged_pending) {
         WS_HIP(hipEventSynchronize(pl->staged_ev));
@@ -487,7 +499,8 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     // each gridding work-group's share of the call's record visits (a row's taps reach about
     // (W + H - 2) / H + 1 strips)
     const int64_t visits = bt.total * (int64_t)((g.support + g.H - 2) / g.H + 1);
-    const int64_t share = std::max<int64_t>(kMinPart, visits / std::max(1, pl->persist_blocks));
+    const int64_t share = pl->no_split ? int64_t(0x3FFFFFFF)
+                                       : std::max<int64_t>(kMinPart, visits / std::max(1, pl->persist_blocks));
     hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nbk, 256)), dim3(256), 0, s, nch, pl->offsets, g,
                        pl->occ, pl->plane_occ, pl->list, pl->list_aux, pl->list_cap,
                        (uint32_t)std::min<int64_t>(share, 0x3FFFFFFF), pl->scalars, pl->worklist);
@@ -670,8 +683,8 @@ wsimg_status for_each_allocation(wsimg_plan* pl, F&& f) {
     WS_ALLOC(occ, nbt, "occupancy");
     WS_ALLOC(list, sizeof(uint32_t) * pl->list_cap, "strip work list");
     WS_ALLOC(list_aux, sizeof(uint32_t) * pl->list_cap, "strip work list parts");
-    WS_ALLOC(split_acc, (size_t)kMaxSplit * pl->lds1, "split strip sums");
-    WS_ALLOC(split_done, sizeof(uint32_t) * kMaxSplit, "split strip counters");
+    WS_ALLOC(split_acc, pl->no_split ? 256 : (size_t)kMaxSplit * pl->lds1, "split strip sums");
+    WS_ALLOC(split_done, pl->no_split ? 256 : sizeof(uint32_t) * kMaxSplit, "split strip counters");
     WS_ALLOC(plane_occ, (size_t)g.nw * mc, "plane occupancy");
     WS_ALLOC(sflags, sizeof(uint16_t) * mc * g.nw * (size_t)(g.n >> pl->lr2), "stacking strip flags");
     WS_ALLOC(key, sizeof(uint32_t) * rows, "keys");
@@ -763,6 +776,110 @@ wsimg_status create(wsimg_plan** out, const wsimg_params* p, int64_t max_vis, in
     return WSIMG_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// The allocation-free entry point: a transient plan whose scratch is carved from one static
+// device array instead of hipMalloc'ed buffers.  Every GPU the library runs on holds its own
+// copy of the array (from module load to process end).  In host code the array's name is
+// only a stand-in for its device address, so the address of this device's copy is taken once
+// per device with hipGetSymbolAddress (with that device current) and only that address is
+// ever handed to kernels or copies.
+constexpr size_t kStaticTableBytes = size_t(256) << 10;   // twiddles, taper, kernel polynomials
+static_assert(WSIMG_NOALLOC_SCRATCH_BYTES > kStaticTableBytes, "static scratch too small");
+static __device__ __align__(256) unsigned char scratch[WSIMG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+struct StaticScratch {
+    void* ptr = nullptr;            // this device's copy of `scratch`
+    bool tables_valid = false;      // the table region holds the tables of `key`
+    double key[6] = {0, 0, 0, 0, 0, 0};
+};
+std::mutex g_scratch_mu;
+StaticScratch g_scratch[kMaxDevices];
+
+// The table key of a plan: every quantity upload_tables reads.
+void table_key(const wsimg_plan* pl, double key[6]) {
+    key[0] = pl->p.precision; key[1] = pl->g.n; key[2] = pl->g.n_img; key[3] = pl->p.support;
+    key[4] = pl->p.beta; key[5] = 1.0;
+}
+
+template <typename R>
+wsimg_status upload_tables_async(wsimg_plan* pl) {
+    // the tables go out through pageable host vectors: wait for the copies before they die
+    if (auto r = upload_tables<R>(pl)) return r;
+    WS_HIP(hipStreamSynchronize(pl->stream));
+    return WSIMG_OK;
+}
+
+wsimg_status image_noalloc(const wsimg_params* p, int64_t n_vis, const double* uvw, const void* vis,
+                           const void* wts, double freq_hz, void* image_out, void* hip_stream,
+                           wsimg_stats* stats) {
+    if (n_vis < 0) return fail(WSIMG_E_INVALID, "n_vis < 0");
+    wsimg_plan pl;
+    if (auto r = plan_geometry(&pl, p, n_vis, 1)) return r;
+    pl.direct_channels = true;
+    pl.no_split = true;
+    pl.stream = (hipStream_t)hip_stream;
+    // sizes first (host arithmetic): the tables at the start of the array, the rest after them
+    auto is_table = [&pl](void** field) { return field == &pl.tw || field == &pl.inv_taper || field == &pl.kbc; };
+    size_t tab_need = 0, need = kStaticTableBytes;
+    for_each_allocation(&pl, [&](void** field, size_t b, const char*) {
+        (is_table(field) ? tab_need : need) += (std::max<size_t>(b, 256) + 255) & ~size_t(255);
+        return WSIMG_OK;
+    });
+    if (tab_need > kStaticTableBytes || need > (size_t)WSIMG_NOALLOC_SCRATCH_BYTES) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "wsimg_image_noalloc: this geometry and n_vis need %zu bytes of scratch; "
+                 "the static scratch holds %zu", need + (tab_need > kStaticTableBytes ? tab_need : 0),
+                 (size_t)WSIMG_NOALLOC_SCRATCH_BYTES);
+        return fail(WSIMG_E_CAPACITY, buf);
+    }
+    if (n_vis > 0 && (!uvw || !vis || !wts)) return fail(WSIMG_E_INVALID, "input pointer is NULL");
+    if (!image_out) return fail(WSIMG_E_INVALID, "output pointer is NULL");
+    if (stats && capturing(&pl)) return fail(WSIMG_E_INVALID, "stats need a host wait: not under graph capture");
+    WS_HIP(hipGetDevice(&pl.device));
+    if (pl.device < 0 || pl.device >= kMaxDevices) return fail(WSIMG_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    StaticScratch& ss = g_scratch[pl.device];
+    if (!ss.ptr) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(WSIMG_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        ss.ptr = ptr;
+    }
+    const bool f32 = p->precision == WSIMG_F32;
+    if (auto r = f32 ? lds_limits<float>(&pl) : lds_limits<double>(&pl)) return r;
+    int cus = 0;
+    WS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl.device));
+    pl.persist_blocks = std::max(1, cus) * std::max(1, (int)((160 * 1024) / std::max<size_t>(pl.lds1, 1)));
+    // carve
+    unsigned char* base = static_cast<unsigned char*>(ss.ptr);
+    size_t tab_off = 0, off = kStaticTableBytes;
+    for_each_allocation(&pl, [&](void** field, size_t b, const char*) {
+        const size_t sz = (std::max<size_t>(b, 256) + 255) & ~size_t(255);
+        size_t& at = is_table(field) ? tab_off : off;
+        *field = base + at;
+        at += sz;
+        return WSIMG_OK;
+    });
+    double key[6];
+    table_key(&pl, key);
+    if (!ss.tables_valid || std::memcmp(key, ss.key, sizeof key) != 0) {
+        ss.tables_valid = false;
+        if (auto r = f32 ? upload_tables_async<float>(&pl) : upload_tables_async<double>(&pl)) return r;
+        std::memcpy(ss.key, key, sizeof key);
+        ss.tables_valid = true;
+    }
+    Batch bt;
+    bt.nch = 1; bt.counts = &n_vis; bt.freqs = &freq_hz; bt.total = n_vis; bt.max_count = n_vis;
+    if (!(freq_hz > 0.0) || !std::isfinite(freq_hz)) return fail(WSIMG_E_INVALID, "freq_hz must be finite and > 0");
+    WS_HIP(hipSetDevice(pl.device));
+    wsimg_status r = f32 ? run_image<float>(&pl, bt, uvw, vis, wts, image_out, false)
+                         : run_image<double>(&pl, bt, uvw, vis, wts, image_out, false);
+    if (r) return r;
+    return finish_call(&pl, 1, stats);
+}
+
 }  // namespace
 
 extern "C" {
@@ -851,6 +968,12 @@ wsimg_status wsimg_predict(wsimg_plan* plan, int64_t n_vis, const double* uvw_m,
 wsimg_status wsimg_grid(wsimg_plan* plan, int64_t n_vis, const double* uvw_m, const void* vis,
                         const void* weights, double freq_hz, void* grid_out, wsimg_stats* stats) {
     return dispatch(plan, 1, &n_vis, uvw_m, vis, weights, &freq_hz, grid_out, stats, true);
+}
+
+wsimg_status wsimg_image_noalloc(const wsimg_params* p, int64_t n_vis, const double* uvw_m, const void* vis,
+                                 const void* weights, double freq_hz, void* image_out, void* hip_stream,
+                                 wsimg_stats* stats) {
+    return image_noalloc(p, n_vis, uvw_m, vis, weights, freq_hz, image_out, hip_stream, stats);
 }
 
 wsimg_status wsimg_set_timing(wsimg_plan* plan, int32_t enable) {

@@ -82,6 +82,22 @@ def test_every_declared_flag_is_accepted_on_host(lib):
         assert L.wsimg_plan_query(ctypes.byref(p), 100, 1, ctypes.byref(info)) == mod.WSIMG_OK, flag
 
 
+def test_noalloc_capacity_checked_on_host(lib):
+    """wsimg_image_noalloc refuses a geometry whose scratch exceeds its static array before
+    any device work (no GPU here), and checks parameters like wsimg_plan_create."""
+    L, mod = lib
+    p = _params(mod, n=4096, n_wplanes=32)
+    st = L.wsimg_image_noalloc(ctypes.byref(p), 7_000_000, None, None, None, 1.4e9, None, None, None)
+    assert st == mod.WSIMG_E_CAPACITY
+    assert b"static scratch" in L.wsimg_last_error()
+    p = _params(mod, support=8)
+    assert L.wsimg_image_noalloc(ctypes.byref(p), 10, None, None, None, 1e9, None, None, None) == mod.WSIMG_E_INVALID
+    p = _params(mod)
+    assert L.wsimg_image_noalloc(ctypes.byref(p), -1, None, None, None, 1e9, None, None, None) == mod.WSIMG_E_INVALID
+    # within the array, a missing output is an argument error (still before any device work)
+    assert L.wsimg_image_noalloc(ctypes.byref(p), 0, None, None, None, 1e9, None, None, None) == mod.WSIMG_E_INVALID
+
+
 def test_fixed_range_and_capacity_rules(lib):
     L, mod = lib
     h = ctypes.c_void_p()
