@@ -27,9 +27,13 @@ template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
 template <typename C> __device__ __forceinline__ C cmuli(C a) { return cmake<C>(-a.y, a.x); }
 template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return cmake<C>(a.x * s, a.y * s); }
 
-// LDS element index with one pad slot per 16 elements: keeps the strided Stockham
-// writes and the 16-wide butterfly reads off common banks.
-__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
+// LDS element index with one pad slot per 2^WSIMG_LDS_PAD_SHIFT elements: keeps the strided
+// Stockham writes and the butterfly reads off common banks (one per 32: a 4096^2 image 2.87 ->
+// 2.85 ms and an 8192^2 one 48.4 -> 47.7 ms against one per 16; one per 8 was slower).
+#ifndef WSIMG_LDS_PAD_SHIFT
+#define WSIMG_LDS_PAD_SHIFT 5
+#endif
+__device__ __forceinline__ int lds_pad(int e) { return e + (e >> WSIMG_LDS_PAD_SHIFT); }
 // Hide a (wave-uniform) pointer's value from the optimiser.  Used on the twiddle table at
 // the top of loops over strips or planes, so its loads stay inside each FFT pass instead of
 // being hoisted out of the loop into registers the passes need.
@@ -39,9 +43,9 @@ __device__ __forceinline__ const T* opaque_ptr(const T* p) {
     return p;
 }
 
-__host__ __device__ __forceinline__ int lds_padded_elems(int e) { return e + (e >> 4) + 1; }
+__host__ __device__ __forceinline__ int lds_padded_elems(int e) { return e + (e >> WSIMG_LDS_PAD_SHIFT) + 1; }
 // padded element count rounded up to an even number, so a double array can follow it
-constexpr int lds_padded_elems_c(int e) { return (e + (e >> 4) + 2) & ~1; }
+constexpr int lds_padded_elems_c(int e) { return (e + (e >> WSIMG_LDS_PAD_SHIFT) + 2) & ~1; }
 
 // Grid position of one row, computed in float64 with the operation order the imaging
 // definition uses:  u = (uvw_u * freq) / c,  x = u / du + n/2  (same for v, y; w likewise

@@ -39,7 +39,7 @@ struct Geom {
     size_t plane_elems;     // elements of one plane of the intermediate: n * n_img
     int H, log2H, S;        // grid rows per strip, strips per plane
     int nb1;                // buckets per channel: nw * S
-    int B, log2B, NB;       // image columns per stacking block, blocks
+    int B, log2B, NB;       // columns per layout block of the intermediate; prediction column blocks
     int fixed_range;
     int unnormalized;       // the image is not divided by the sum of weights
     int fold_w;             // w-folding (rows with w < 0 as their conjugate partners)
@@ -97,6 +97,33 @@ __device__ __forceinline__ R kb_tap(const R* __restrict__ coef, int a, R f) {
 #pragma unroll
     for (int d = D - 1; d >= 0; --d) acc = acc * f + c[d];
     return acc;
+}
+
+// All taps of one axis, centred: g[C + d] = G(d - f) for |d| <= h = (W - 1) / 2, C = WMAX / 2
+// (tap a = h + d of the origin ⌊x + 1/2⌋ - h).  G is even, so tap h + d at offset f is tap
+// h - d at offset -f: with P the polynomial of tap h - d split into its even part E(f^2) and
+// odd part f O(f^2), the pair is E + f O (tap h - d) and E - f O (tap h + d), one evaluation
+// of each half for two taps.
+template <typename R, int WMAX>
+__device__ __forceinline__ void kb_taps_centred(const R* __restrict__ coef, int h, R f, R* g) {
+    constexpr int D = KbDeg<R>::value, C = WMAX / 2;
+    constexpr int DE = D & ~1, DO = (D & 1) ? D : D - 1;      // highest even / odd degree
+    const R f2 = f * f;
+#pragma unroll
+    for (int d = 0; d <= C; ++d) {
+        if (d <= h) {
+            const R* c = coef + (h - d) * (D + 1);
+            R e = c[DE];
+#pragma unroll
+            for (int k = DE - 2; k >= 0; k -= 2) e = e * f2 + c[k];
+            R o = c[DO];
+#pragma unroll
+            for (int k = DO - 2; k >= 1; k -= 2) o = o * f2 + c[k];
+            const R fo = f * o;
+            g[C - d] = e + fo;
+            if (d > 0) g[C + d] = e - fo;
+        }
+    }
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t v) {
@@ -636,14 +663,51 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
 #ifndef WSIMG_F32_LR1
 #define WSIMG_F32_LR1 4
 #endif
-// float stacking: radix 16 from N = 4096 up (1.26 -> 1.18 ms on a 4096^2 image of 32 planes),
-// radix 8 below (1024^2: 1.92 ms against 2.18 ms for 64 channels of 16 planes)
-#ifndef WSIMG_F32_LR2
-#define WSIMG_F32_LR2 4
+// float stacking, per image size (log2 n): radix 16 at 4096^2 (1.16 ms against 1.26 ms with
+// radix 8 for 32 planes), radix 8 at 8192^2 (64 planes: 12.3 ms against 14.3 ms; 1024 threads of
+// 8 pixels keep 4 waves per SIMD where 512 threads of 16 pixels kept 2) and below 4096^2
+// (1024^2: 1.92 ms against 2.18 ms for 64 channels of 16 planes).  WSIMG_F32_LR2_N<log2 n>
+// sets one size (the autotuner's per-shape choices); WSIMG_F32_LR2 overrides every size.
+#ifndef WSIMG_F32_LR2_N12
+#define WSIMG_F32_LR2_N12 4
+#endif
+#ifndef WSIMG_F32_LR2_N13
+#define WSIMG_F32_LR2_N13 3
 #endif
 #ifndef WSIMG_F32_LR2_SMALL
 #define WSIMG_F32_LR2_SMALL 3
 #endif
+template <int LOG2N> constexpr int f32_stack_radix_log2() {
+#ifdef WSIMG_F32_LR2
+    return WSIMG_F32_LR2;
+#else
+#ifdef WSIMG_F32_LR2_N4
+    if (LOG2N == 4) return WSIMG_F32_LR2_N4;
+#endif
+#ifdef WSIMG_F32_LR2_N5
+    if (LOG2N == 5) return WSIMG_F32_LR2_N5;
+#endif
+#ifdef WSIMG_F32_LR2_N6
+    if (LOG2N == 6) return WSIMG_F32_LR2_N6;
+#endif
+#ifdef WSIMG_F32_LR2_N7
+    if (LOG2N == 7) return WSIMG_F32_LR2_N7;
+#endif
+#ifdef WSIMG_F32_LR2_N8
+    if (LOG2N == 8) return WSIMG_F32_LR2_N8;
+#endif
+#ifdef WSIMG_F32_LR2_N9
+    if (LOG2N == 9) return WSIMG_F32_LR2_N9;
+#endif
+#ifdef WSIMG_F32_LR2_N10
+    if (LOG2N == 10) return WSIMG_F32_LR2_N10;
+#endif
+#ifdef WSIMG_F32_LR2_N11
+    if (LOG2N == 11) return WSIMG_F32_LR2_N11;
+#endif
+    return LOG2N == 13 ? WSIMG_F32_LR2_N13 : (LOG2N == 12 ? WSIMG_F32_LR2_N12 : WSIMG_F32_LR2_SMALL);
+#endif
+}
 // base radix of the prediction's column pass (the stacking pass's transpose)
 #ifndef WSIMG_F32_LR2A
 #define WSIMG_F32_LR2A 3
@@ -679,6 +743,28 @@ static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
 #ifndef WSIMG_F64_PX2
 #define WSIMG_F64_PX2 4096
 #endif
+// Per image size: at 8192^2 a strip is one grid row, and with one column per layout block each
+// row element went to its own 64 KB-strided address (8-byte stores: 32 GB written for 9.3 GB of
+// strips on the LOFAR-shaped image).  Eight float columns per block make every row store a
+// whole 64-byte segment (gridding 28.9 -> 20.8 ms, stacking 12.1 -> 13.9 ms as each stacking
+// block now reads 8 of every 64 bytes: 47.7 -> 41.4 ms per image; 2, 4 and 16 columns: 45.9,
+// 43.3, 43.4 ms).  In double, 1, 2, 4 and 8 columns time alike (101-104 ms): one is kept.
+#ifndef WSIMG_F32_PX2_N13
+#define WSIMG_F32_PX2_N13 65536
+#endif
+#ifndef WSIMG_F64_PX2_N13
+#define WSIMG_F64_PX2_N13 8192
+#endif
+#ifndef WSIMG_F32_PX2_N12
+#define WSIMG_F32_PX2_N12 WSIMG_F32_PX2
+#endif
+#ifndef WSIMG_F64_PX2_N12
+#define WSIMG_F64_PX2_N12 WSIMG_F64_PX2
+#endif
+template <typename R, int LOG2N> constexpr int layout_pixels() {
+    if constexpr (sizeof(R) == 4) return LOG2N == 13 ? WSIMG_F32_PX2_N13 : (LOG2N == 12 ? WSIMG_F32_PX2_N12 : WSIMG_F32_PX2);
+    else return LOG2N == 13 ? WSIMG_F64_PX2_N13 : (LOG2N == 12 ? WSIMG_F64_PX2_N12 : WSIMG_F64_PX2);
+}
 // image columns per stacking block (0: all B columns of a layout block).  float: one, so that
 // several blocks share a CU and one block's barriers overlap another's work (a 4096^2 image
 // of 32 planes: 1.44 -> 1.26 ms with radix-8 passes, 1.18 ms with radix 16: 256 threads per
@@ -693,6 +779,10 @@ static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
 #ifndef WSIMG_COLS_XCD_MAP
 #define WSIMG_COLS_XCD_MAP 1
 #endif
+// column blocks per XCD group (0: one 128-byte line of image pixels per row)
+#ifndef WSIMG_COLS_XCD_Q
+#define WSIMG_COLS_XCD_Q 0
+#endif
 
 // bytes of the stacking pass's LDS plane-flag table: the largest plane count a plan takes
 constexpr size_t kPlaneTab = 4096;
@@ -701,7 +791,7 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int N = 1 << LOG2N;
     // base radices (log2), at most log2(N) - 1 so that a transform has two passes or more
     static constexpr int LR1_0 = sizeof(R) == 4 ? WSIMG_F32_LR1 : WSIMG_F64_LR1;
-    static constexpr int LR2_0 = sizeof(R) == 4 ? (LOG2N >= 12 ? WSIMG_F32_LR2 : WSIMG_F32_LR2_SMALL) : WSIMG_F64_LR2;
+    static constexpr int LR2_0 = sizeof(R) == 4 ? f32_stack_radix_log2<LOG2N>() : WSIMG_F64_LR2;
     static constexpr int LR1 = LR1_0 < LOG2N ? LR1_0 : LOG2N - 1;
     static constexpr int LR2 = LR2_0 < LOG2N ? LR2_0 : LOG2N - 1;
     static constexpr int E1 = 1 << LR1, E2 = 1 << LR2;
@@ -714,19 +804,23 @@ template <typename R, int LOG2N> struct Shape {
                               : (CAP1 / N < 4 ? (CAP1 / N < 1 ? 1 : CAP1 / N) : 4);
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
     static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);
-    static constexpr int PX2 = sizeof(R) == 4 ? WSIMG_F32_PX2 : WSIMG_F64_PX2;
-    // the intermediate holds B columns side by side per row (the gridding pass's write unit and
-    // the prediction's column block); a stacking block takes BS <= B of them
+    static constexpr int PX2 = layout_pixels<R, LOG2N>();
+    // the intermediate holds B columns side by side per row (the gridding pass's write unit); a
+    // stacking block takes BS <= B of them and a prediction column block BA <= B
     static constexpr int B0 = PX2 / N < N / 2 ? PX2 / N : N / 2;   // at most half a (padded) grid
     static constexpr int B = B0 < 1 ? 1 : B0;
+    // the column blocks the work-groups of the column passes can hold in LDS
+    static constexpr int PXA = sizeof(R) == 4 ? WSIMG_F32_PX2 : WSIMG_F64_PX2;
+    static constexpr int BA0 = PXA / N < 1 ? 1 : PXA / N;
+    static constexpr int BA = BA0 < B ? BA0 : B;
     static constexpr int BS0 = sizeof(R) == 4 ? WSIMG_F32_BS : WSIMG_F64_BS;
-    static constexpr int BS = (BS0 <= 0 || BS0 > B) ? B : BS0;
-    static_assert((BS & (BS - 1)) == 0, "stacking columns per block: a power of two");
+    static constexpr int BS = BS0 <= 0 ? BA : (BS0 > B ? B : BS0);
+    static_assert((BS & (BS - 1)) == 0 && (BA & (BA - 1)) == 0, "column blocks: powers of two");
     static constexpr int NT2 = (BS * N / E2) < 64 ? 64 : (BS * N / E2);   // stacking
-    static constexpr int NT2A = (B * N >> LR2A) < 64 ? 64 : (B * N >> LR2A);   // prediction column pass
+    static constexpr int NT2A = (BA * N >> LR2A) < 64 ? 64 : (BA * N >> LR2A);   // prediction column pass
     static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
     static constexpr size_t LDS1_BYTES = (size_t)LDS1 * sizeof(double2);   // float64 accumulation
-    static constexpr int LDS2 = lds_padded_elems_c(B * N);                 // complex elements
+    static constexpr int LDS2 = lds_padded_elems_c(BA * N);                // complex elements
     static constexpr size_t LDS2_BYTES = (size_t)LDS2 * 2 * sizeof(R);      // column pass of prediction
     static constexpr int LDS2S = lds_padded_elems_c(BS * N);               // stacking FFT buffer
     static constexpr size_t LDS2S_BUF = (size_t)LDS2S * 2 * sizeof(R);
@@ -799,7 +893,8 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
     for (int e = tid; e < SH::LDS1; e += NT) acc[e] = make_double2(0.0, 0.0);
     __syncthreads();
 
-    const int W = g.support;
+    const int W = g.support, hW = g.half;
+    constexpr int TC = WMAX / 2;               // centre slot of the tap arrays
     int s_lo = (row0 - (W - 1)) >> LOG2H;
     if (s_lo < 0) s_lo = 0;
     constexpr int shift = FFT ? (n >> 1) : 0;   // place cell q at (q + n/2) mod n: the centring
@@ -824,11 +919,12 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
         const uint32_t re = r + chunk < vend ? r + chunk : vend;
         int sp = s_lo;
         uint32_t bend = offsets[(size_t)(bucket0 + sp + 1) << kLogReplicas];
+        // run sums and tap weights by centred tap slot t = C + d (tap a = h + d, |d| <= h)
         double2 sum[RW][WMAX];
 #pragma unroll
         for (int rr = 0; rr < RW; ++rr)
 #pragma unroll
-            for (int a = 0; a < WMAX; ++a) sum[rr][a] = make_double2(0.0, 0.0);
+            for (int t = 0; t < WMAX; ++t) sum[rr][t] = make_double2(0.0, 0.0);
         int cq = -1, cp = 0;
         // dirty: the sums hold a run not yet added to the strip.  A flush leaves the sums as
         // they are; the next record that adds taps scales them by 0 (keep) in the same fused
@@ -842,12 +938,13 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                 const int b = rlo + rr - cp;
                 if ((unsigned)b < (unsigned)W) {
                     const int lrow = (rlo + rr - row0) << LOG2N;
+                    const int q_c = cq + hW + shift - TC;      // cell of slot t: q_c + t
 #pragma unroll
-                    for (int a = 0; a < WMAX; ++a) {
-                        if (a < W) {
-                            double2* dst = &acc[lds_pad(lrow + ((cq + a + shift) & nmask))];
-                            atomicAdd(&dst->x, sum[rr][a].x);
-                            atomicAdd(&dst->y, sum[rr][a].y);
+                    for (int t = 0; t < WMAX; ++t) {
+                        if (t - TC <= hW && TC - t <= hW) {
+                            double2* dst = &acc[lds_pad(lrow + ((q_c + t) & nmask))];
+                            atomicAdd(&dst->x, sum[rr][t].x);
+                            atomicAdd(&dst->y, sum[rr][t].y);
                         }
                     }
                 }
@@ -869,9 +966,7 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
             }
             if (rlo + RW - 1 < p0 || rlo > p0 + W - 1) return;       // no tap row in this walk
             R gx[WMAX];
-#pragma unroll
-            for (int a = 0; a < WMAX; ++a)
-                if (a < W) gx[a] = kb_tap<R>(kbc, a, fr.x);
+            kb_taps_centred<R, WMAX>(kbc, hW, fr.x, gx);
             // every row of the walk, with zero weight on the rows the record does not reach
             const double keep = dirty ? 1.0 : 0.0;
             dirty = true;
@@ -882,10 +977,10 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
                 const R gy = reach ? kb_tap<R>(kbc, reach ? b : 0, fr.y) : (R)0;
                 const R vr = v.x * gy, vi = v.y * gy;
 #pragma unroll
-                for (int a = 0; a < WMAX; ++a) {
-                    if (a < W) {
-                        sum[rr][a].x = __builtin_fma(sum[rr][a].x, keep, (double)(vr * gx[a]));
-                        sum[rr][a].y = __builtin_fma(sum[rr][a].y, keep, (double)(vi * gx[a]));
+                for (int t = 0; t < WMAX; ++t) {
+                    if (t - TC <= hW && TC - t <= hW) {
+                        sum[rr][t].x = __builtin_fma(sum[rr][t].x, keep, (double)(vr * gx[t]));
+                        sum[rr][t].y = __builtin_fma(sum[rr][t].y, keep, (double)(vi * gx[t]));
                     }
                 }
             }
@@ -1106,17 +1201,23 @@ template <typename R> struct ColsWaves {
     static constexpr int value = sizeof(R) == 4 ? WSIMG_F32_COLS_WAVES_PER_EU : WSIMG_F64_COLS_WAVES_PER_EU;
 };
 
-// Stacking block index -> block of BS image columns.  G = B / BS blocks read the same layout
-// blocks of the intermediate (each B-column row chunk); work-groups go to the 8 XCDs round-robin,
-// so the G of a layout block are given indices of one XCD, dispatched close together, and the
-// chunks fetched by the first are read by the others from that XCD's L2.
-template <int G> __device__ __forceinline__ int stack_block(int bid, int nblk) {
-    if constexpr (G == 1 || !WSIMG_COLS_XCD_MAP) {
+// Stacking block index -> block of BS image columns.  Work-groups go to the 8 XCDs round-robin
+// (block bid to XCD bid mod 8, as its slot bid / 8 there), so a group of Q consecutive column
+// blocks is given Q consecutive slots of one XCD: they run at the same time on that XCD, and
+//   * the G = B / BS blocks that read the same layout blocks of the intermediate (each B-column
+//     row chunk) find the chunks the first of them fetched in the XCD's L2;
+//   * the image rows they write (BS columns each, at the end) merge into whole cache lines in
+//     the L2 before they reach HBM: Q blocks cover 128 bytes of every image row.
+// Q is a multiple of G, so a layout block's readers stay in one group.
+template <typename R, int G, int BS> __device__ __forceinline__ int stack_block(int bid, int nblk) {
+    constexpr int Q0 = WSIMG_COLS_XCD_Q > 0 ? WSIMG_COLS_XCD_Q : 128 / (int)sizeof(R) / BS;
+    constexpr int Q = WSIMG_COLS_XCD_MAP ? (Q0 > G ? Q0 : G) : 1;
+    if constexpr (Q <= 1) {
         return bid;
     } else {
-        if (nblk % (8 * G) != 0) return bid;
+        if (nblk % (8 * Q) != 0) return bid;
         const int xcd = bid & 7, slot = bid >> 3;
-        return ((((slot / G) << 3) + xcd) * G) + (slot % G);
+        return ((((slot / Q) << 3) + xcd) * Q) + (slot % Q);
     }
 }
 
@@ -1145,7 +1246,7 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
     double* nm1s = reinterpret_cast<double*>(lds0 + SH::LDS2S);
     double nm1r[SH::NM1_LDS ? 1 : E];
     nm1r[0] = 0.0;
-    const int jb = stack_block<B / BS>(blockIdx.x, gridDim.x), c = blockIdx.y;
+    const int jb = stack_block<R, B / BS, BS>(blockIdx.x, gridDim.x), c = blockIdx.y;
     const int crop = PAD ? g.crop : 0, nimg = PAD ? g.n_img : n;
     const int tid = threadIdx.x;
     // every thread takes part in the first pass unless the block was widened to a wave
@@ -1330,12 +1431,14 @@ k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ o
     using C = typename Cx<R>::T;
     using SH = Shape<R, LOG2N>;
     constexpr int n = SH::N, nmask = n - 1, hn = n >> 1;
-    constexpr int B = SH::B, NT = SH::NT2A, LOG2B = Log2Of<B>::value_any, LR = SH::LR2A;
-    constexpr int elems = B * n;
+    constexpr int B = SH::B, BA = SH::BA, NT = SH::NT2A, LOG2B = Log2Of<B>::value_any, LR = SH::LR2A;
+    constexpr int LOG2BA = Log2Of<BA>::value_any, LOG2GA = LOG2B - LOG2BA;
+    constexpr int elems = BA * n;
     constexpr int PER = (elems + NT - 1) / NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* lds = reinterpret_cast<C*>(smem_raw);
-    const int jb = blockIdx.x, c = blockIdx.y;
+    // block x = BA columns starting at image column x * BA: layout block jb, its columns col0..
+    const int jb = blockIdx.x >> LOG2GA, col0 = (blockIdx.x & ((1 << LOG2GA) - 1)) << LOG2BA, c = blockIdx.y;
     const int tid = threadIdx.x;
     const uint8_t* pocc = plane_occ + (size_t)c * g.nw;
     const uint8_t* socc = occ + (size_t)c * g.nb1;
@@ -1351,7 +1454,7 @@ k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ o
         nm1[t] = 0.0;
         if (PER * NT == elems || e < elems) {
             const int col = e >> LOG2N, ip = e & nmask;
-            const int i = ((ip + hn) & nmask) - g.crop, j = (jb << LOG2B) + col;   // image pixel
+            const int i = ((ip + hn) & nmask) - g.crop, j = (jb << LOG2B) + col0 + col;   // image pixel
             if (i >= 0 && i < g.n_img) {       // outside the image (a padded grid): zero
                 xt[t] = img[(size_t)i * g.n_img + j] * inv_taper[i] * inv_taper[j];
                 const double l = (double)(j - (g.n_img >> 1)) * g.pixel, m = (double)(i - (g.n_img >> 1)) * g.pixel;
@@ -1387,17 +1490,17 @@ k_adj_cols(Geom g, const Scalars* __restrict__ sc, const uint8_t* __restrict__ o
             }
         }
         __syncthreads();
-        fft_rows_lds<LOG2N, LR, B, NT>(lds, tw);
-        C* dst = inter + (size_t)(c * g.nw + k) * g.plane_elems + (size_t)jb * elems;
+        fft_rows_lds<LOG2N, LR, BA, NT>(lds, tw);
+        C* dst = inter + (size_t)(c * g.nw + k) * g.plane_elems + (size_t)jb * B * n + col0;
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
-            const int f = tid + t * NT;       // [p'][col] order: contiguous in the intermediate
+            const int f = tid + t * NT;       // [p'][col] order: BA contiguous columns of each row
             if (PER * NT == elems || f < elems) {
-                const int pp = f >> LOG2B, col = f & (B - 1);
+                const int pp = f >> LOG2BA, col = f & (BA - 1);
                 const int p = (pp + hn) & nmask;
                 if (socc[k * g.S + (p >> g.log2H)]) {
                     const C v = lds[lds_pad((col << LOG2N) + pp)];
-                    dst[f] = cmake<C>(v.x, -v.y);
+                    dst[(size_t)pp * B + col] = cmake<C>(v.x, -v.y);
                 }
             }
         }

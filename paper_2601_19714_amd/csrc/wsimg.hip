@@ -52,6 +52,7 @@ struct wsimg_plan {
     Geom g{};
     int nt1 = 0, nt2 = 0, nt2a = 0;  // threads of the gridding, stacking and prediction column work-groups
     int bs = 1;                      // image columns per stacking work-group
+    int ba = 1;                      // image columns per prediction column work-group
     size_t lds1 = 0, lds2 = 0, lds2s = 0;   // their dynamic LDS bytes (lds2s: stacking)
     int64_t nb = 0;                // buckets per channel
     size_t cbytes = 0, rbytes = 0; // complex / real element bytes
@@ -202,6 +203,7 @@ wsimg_status fill_shape(wsimg_plan* pl) {
     pl->nt1 = SH::NT1;
     pl->nt2 = SH::NT2;
     pl->nt2a = SH::NT2A;
+    pl->ba = SH::BA;
     pl->bs = SH::BS;
     pl->lds1 = SH::LDS1_BYTES;
     pl->lds2 = SH::LDS2_BYTES;
@@ -215,6 +217,10 @@ template <typename R, int LOG2N>
 wsimg_status set_lds_limits(wsimg_plan* pl) {
     using SH = Shape<R, LOG2N>;
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, 7>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
+    WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, 9>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
+    WS_HIP(hipFuncSetAttribute((const void*)k_grid_only<R, LOG2N, 9>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, kMaxSupport>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
@@ -276,8 +282,10 @@ wsimg_status launch_grid_w(wsimg_plan* pl, int nch, bool fft, void* out) {
 
 template <typename R, int LOG2N>
 wsimg_status launch_grid_rows(wsimg_plan* pl, int nch, bool fft, void* out) {
-    return pl->g.support <= 7 ? launch_grid_w<R, LOG2N, 7>(pl, nch, fft, out)
-                              : launch_grid_w<R, LOG2N, kMaxSupport>(pl, nch, fft, out);
+    // register classes of the gridding walk: supports up to 7, exactly 9, up to 15
+    if (pl->g.support <= 7) return launch_grid_w<R, LOG2N, 7>(pl, nch, fft, out);
+    if (pl->g.support == 9) return launch_grid_w<R, LOG2N, 9>(pl, nch, fft, out);
+    return launch_grid_w<R, LOG2N, kMaxSupport>(pl, nch, fft, out);
 }
 
 template <typename R, int LOG2N>
@@ -649,7 +657,7 @@ wsimg_status plan_geometry(wsimg_plan* pl, const wsimg_params* p, int64_t max_vi
     if (auto r = f32 ? shape_of<float>(pl) : shape_of<double>(pl)) return r;
     pl->nb = (int64_t)g.nw * g.S;
     g.nb1 = (int)pl->nb;
-    g.NB = n_img / g.B;             // stacking blocks cover the image's columns only
+    g.NB = n_img / pl->ba;          // prediction column blocks cover the image's columns only
     if (pl->nb * max_channels > kMaxBucketsTotal)
         return fail(WSIMG_E_UNSUPPORTED, "max_channels x n_wplanes x strips exceeds 2^25 sort buckets");
     pl->list_cap = (uint32_t)((size_t)pl->nb * max_channels + (size_t)kMaxSplit * kMaxParts);

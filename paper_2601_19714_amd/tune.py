@@ -7,8 +7,9 @@ in csrc/kernels.hpp.  This tool compiles a set of candidate macro settings and t
 the GPU on synthetic workloads, then records the fastest in tuned.json, which build.py adds
 to its hipcc line.
 
-  python -m paper_2601_19714_amd.tune build [--out DIR]                 (CPU: compile)
-  python -m paper_2601_19714_amd.tune time [--dir DIR] [--workloads c2,c4] [--steps K]
+  python -m paper_2601_19714_amd.tune build [--out DIR] [--workloads c2,c3,c4] [--only a,b]
+                                                                        (CPU: compile)
+  python -m paper_2601_19714_amd.tune time [--dir DIR] [--workloads c2,c3,c4] [--steps K]
                                                                         (GPU: time, write tuned.json)
 Each candidate is timed in a child process of its own (one library per process).
 """
@@ -28,33 +29,60 @@ ROOT = os.path.dirname(HERE)
 TUNED = os.path.join(HERE, "tuned.json")
 DEFAULT_DIR = os.path.join(HERE, "_tune")
 
-# name -> extra macro definitions (the empty set is the source defaults)
+# name -> extra macro definitions (the empty set is the source defaults).  A candidate whose
+# flags hold "{L}" is per-shape: it is built and judged separately for each image size of the
+# timed workloads (L = log2 of the image side), and the fastest per-shape candidate of each size
+# is kept for that size only.  The others are global: kept when their geometric-mean time over
+# all workloads beats the defaults.
 CANDIDATES = {
     "defaults": [],
-    "stack_r8": ["-DWSIMG_F32_LR2=3"],
+    "stack_r8": ["-DWSIMG_F32_LR2_N{L}=3"],
+    "stack_r16": ["-DWSIMG_F32_LR2_N{L}=4"],
     "stack_b2": ["-DWSIMG_F32_BS=0", "-DWSIMG_F32_LR2=3"],
     "strip_rows_by_cells": ["-DWSIMG_STRIP_ROWS_SMALL=0"],
     "chunk32": ["-DWSIMG_GRID_CHUNK_MAX=32"],
     "tw_table": ["-DWSIMG_TW_DERIVE=0"],
     "walk128": ["-DWSIMG_WALK_VGPRS=128"],
+    "xcd_pairs": ["-DWSIMG_COLS_XCD_Q=1"],
 }
 
-WORKLOADS = {"c1": 1, "c2": 2, "c4": 4, "c5": 5}
-# a candidate replaces the defaults only when its geometric-mean time is this much lower
+WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5}
+# log2 of each workload's image side (the tuned float32 path)
+WORKLOAD_LOG2N = {"c1": 8, "c2": 12, "c3": 13, "c4": 10, "c5": 11}
+# a candidate replaces the defaults only when its time is this much lower
 NOISE = 0.01
 
 
-def build_all(out: str, names=None):
+def per_shape(name: str) -> bool:
+    return any("{L}" in f for f in CANDIDATES[name])
+
+
+def variants(workloads):
+    """(library name, candidate, log2 n or None, flags) for every library to build."""
+    out = []
+    shapes = sorted({WORKLOAD_LOG2N[w] for w in workloads})
+    for name, flags in CANDIDATES.items():
+        if per_shape(name):
+            for L in shapes:
+                out.append((f"{name}_n{L}", name, L, [f.replace("{L}", str(L)) for f in flags]))
+        else:
+            out.append((name, name, None, list(flags)))
+    return out
+
+
+def build_all(out: str, workloads, names=None):
     from . import build as _build
     os.makedirs(out, exist_ok=True)
     procs = []
-    for name in names or CANDIDATES:
-        lib = os.path.join(out, f"libwsimg_{name}.so")
-        cmd = [_build.hipcc()] + _build.flags() + CANDIDATES[name] + [_build.SRC, "-o", lib]
-        procs.append((name, subprocess.Popen(cmd, stderr=subprocess.DEVNULL)))
-    failed = [name for name, p in procs if p.wait() != 0]
-    for name, _ in procs:
-        print(f"{name}: {'FAILED' if name in failed else 'ok'}", flush=True)
+    for lib_name, name, _, flags in variants(workloads):
+        if names and name not in names:
+            continue
+        lib = os.path.join(out, f"libwsimg_{lib_name}.so")
+        cmd = [_build.hipcc()] + _build.flags() + flags + [_build.SRC, "-o", lib]
+        procs.append((lib_name, subprocess.Popen(cmd, stderr=subprocess.DEVNULL)))
+    failed = [n for n, p in procs if p.wait() != 0]
+    for n, _ in procs:
+        print(f"{n}: {'FAILED' if n in failed else 'ok'}", flush=True)
     return failed
 
 
@@ -104,38 +132,66 @@ def _time_one(lib: str, workload: str, steps: int, warmup: int):
     print(json.dumps({"ms": 1e3 * (time.perf_counter() - t0) / steps}), flush=True)
 
 
+def _run_child(lib: str, wl: str, steps: int, warmup: int, timeout: int) -> float:
+    cmd = [sys.executable, "-m", "paper_2601_19714_amd.tune", "_run", "--lib", lib, "--workload", wl,
+           "--steps", str(steps), "--warmup", str(warmup)]
+    r = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=timeout)
+    if r.returncode != 0:
+        print(f"{os.path.basename(lib)} {wl}: failed (exit {r.returncode}); stopping", flush=True)
+        print(r.stderr[-2000:], flush=True)
+        raise SystemExit(r.returncode or 1)
+    return json.loads(r.stdout.strip().splitlines()[-1])["ms"]
+
+
 def time_all(src: str, workloads, steps: int, warmup: int, timeout: int):
-    results = {}
-    for name in CANDIDATES:
-        lib = os.path.join(src, f"libwsimg_{name}.so")
+    """Time every built variant on the workloads it applies to; choose per shape and globally."""
+    results = {}            # library name -> workload -> ms
+    for lib_name, name, L, _ in variants(workloads):
+        lib = os.path.join(src, f"libwsimg_{lib_name}.so")
         if not os.path.exists(lib):
-            print(f"{name}: not built, skipped", flush=True)
+            print(f"{lib_name}: not built, skipped", flush=True)
             continue
-        results[name] = {}
+        results[lib_name] = {}
         for wl in workloads:
-            cmd = [sys.executable, "-m", "paper_2601_19714_amd.tune", "_run", "--lib", lib, "--workload", wl,
-                   "--steps", str(steps), "--warmup", str(warmup)]
-            r = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=timeout)
-            if r.returncode != 0:
-                print(f"{name} {wl}: failed (exit {r.returncode}); stopping", flush=True)
-                print(r.stderr[-2000:], flush=True)
-                raise SystemExit(r.returncode or 1)
-            ms = json.loads(r.stdout.strip().splitlines()[-1])["ms"]
-            results[name][wl] = ms
-            print(f"{name} {wl}: {ms:.3f} ms", flush=True)
+            if L is not None and WORKLOAD_LOG2N[wl] != L:
+                continue
+            results[lib_name][wl] = ms = _run_child(lib, wl, steps, warmup, timeout)
+            print(f"{lib_name} {wl}: {ms:.3f} ms", flush=True)
     base = results.get("defaults")
+    if not base:
+        raise SystemExit("the defaults library was not timed")
+    flags, chosen = [], {}
+    # per shape: the fastest per-shape candidate of each size (summed over that size's workloads)
+    for L in sorted({WORKLOAD_LOG2N[w] for w in workloads}):
+        wls = [w for w in workloads if WORKLOAD_LOG2N[w] == L]
+        t0 = sum(base[w] for w in wls)
+        best, tbest = "defaults", t0
+        for lib_name, name, LL, fl in variants(workloads):
+            if LL == L and lib_name in results and all(w in results[lib_name] for w in wls):
+                t = sum(results[lib_name][w] for w in wls)
+                if t < tbest * (1.0 - NOISE) and t < t0 * (1.0 - NOISE):
+                    best, tbest = lib_name, t
+        entry = {"candidate": best, "ms": tbest, "defaults_ms": t0, "workloads": wls, "flags": []}
+        if best != "defaults":
+            entry["flags"] = next(fl for ln, _, _, fl in variants(workloads) if ln == best)
+            flags += entry["flags"]
+        chosen[f"f32/{L}"] = entry
+    # global: geometric mean over all workloads
     score = {}
-    for name, res in results.items():
-        if len(res) == len(workloads) and base:
-            score[name] = math.exp(sum(math.log(res[wl] / base[wl]) for wl in workloads) / len(workloads))
-    best = min(score, key=score.get)
-    if score[best] > 1.0 - NOISE:        # within timing noise of the source defaults: keep them
-        best = "defaults"
-    rec = {"flags": CANDIDATES[best], "candidate": best, "score_vs_defaults": score,
+    for lib_name, name, L, _ in variants(workloads):
+        res = results.get(lib_name, {})
+        if L is None and len(res) == len(workloads):
+            score[lib_name] = math.exp(sum(math.log(res[wl] / base[wl]) for wl in workloads) / len(workloads))
+    gbest = min(score, key=score.get)
+    if score[gbest] > 1.0 - NOISE:        # within timing noise of the source defaults: keep them
+        gbest = "defaults"
+    flags += CANDIDATES[gbest]
+    rec = {"flags": flags, "per_shape": chosen, "global": {"candidate": gbest, "score_vs_defaults": score},
            "ms": results, "workloads": list(workloads), "steps": steps}
     with open(TUNED, "w") as fh:
         json.dump(rec, fh, indent=1)
-    print(f"best: {best} ({score[best]:.3f} of the defaults' time); written to {TUNED}", flush=True)
+    print(f"per shape: { {k: v['candidate'] for k, v in chosen.items()} }; global: {gbest}; "
+          f"flags {flags}; written to {TUNED}", flush=True)
     return rec
 
 
@@ -144,9 +200,11 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     b = sub.add_parser("build")
     b.add_argument("--out", default=DEFAULT_DIR)
+    b.add_argument("--workloads", default="c2,c3,c4")
+    b.add_argument("--only", default="", help="comma-separated candidate names (default: all)")
     t = sub.add_parser("time")
     t.add_argument("--dir", default=DEFAULT_DIR)
-    t.add_argument("--workloads", default="c2,c4")
+    t.add_argument("--workloads", default="c2,c3,c4")
     t.add_argument("--steps", type=int, default=10)
     t.add_argument("--warmup", type=int, default=2)
     t.add_argument("--timeout", type=int, default=240)
@@ -157,7 +215,9 @@ def main(argv=None):
     r.add_argument("--warmup", type=int, default=2)
     a = ap.parse_args(argv)
     if a.cmd == "build":
-        sys.exit(1 if build_all(a.out) else 0)
+        wls = [w for w in a.workloads.split(",") if w]
+        only = [x for x in a.only.split(",") if x] or None
+        sys.exit(1 if build_all(a.out, wls, only) else 0)
     if a.cmd == "time":
         time_all(a.dir, [w for w in a.workloads.split(",") if w], a.steps, a.warmup, a.timeout)
     if a.cmd == "_run":

@@ -43,13 +43,16 @@ MAX_LDS = 160 * 1024
 CUS = 256                     # MI355X compute units (the persistent grid's size)
 
 
+PAD_SHIFT = 5                 # one LDS pad slot per 32 elements
+
+
 def padded(e):
-    """Padded LDS elements (one slot per 16), rounded up to an even count."""
-    return (e + (e >> 4) + 2) & ~1
+    """Padded LDS elements (one slot per 32), rounded up to an even count."""
+    return (e + (e >> PAD_SHIFT) + 2) & ~1
 
 
 def lds_pad(e):
-    return e + (e >> 4)
+    return e + (e >> PAD_SHIFT)
 
 
 def shape(prec, log2n):
@@ -57,15 +60,17 @@ def shape(prec, log2n):
     f32 = prec == "f32"
     N = 1 << log2n
     lr1 = min(4, log2n - 1)
-    lr2 = min((4 if log2n >= 12 else 3) if f32 else 3, log2n - 1)
+    lr2 = min((4 if log2n == 12 else 3) if f32 else 3, log2n - 1)
     cap1 = 8192 if log2n >= 12 else 4096
     h0 = 2 if log2n < 12 else min(4, max(1, cap1 // N))
     H = min(h0, N // 2)
     nt1 = max(64, H * N >> lr1)
-    px2 = 8192 if f32 else 4096
+    pxa = 8192 if f32 else 4096                              # column-pass work-group pixels
+    px2 = (65536 if f32 else 8192) if log2n == 13 else pxa   # layout block pixels
     B = max(1, min(px2 // N, N // 2))
+    BA = min(max(1, pxa // N), B)
     bs0 = 1 if f32 else 0
-    BS = B if (bs0 <= 0 or bs0 > B) else bs0
+    BS = BA if bs0 <= 0 else min(bs0, B)
     E2 = 1 << lr2
     nt2 = max(64, BS * N // E2)
     cb = 8 if f32 else 16
@@ -78,8 +83,8 @@ def shape(prec, log2n):
 
 
 def walk_rows(W):
-    """Register rows per gridding walk for the support class (W <= 7: 7 taps, else 15)."""
-    wmax = 7 if W <= 7 else 15
+    """Register rows per gridding walk for the support class (W <= 7: 7 taps, W = 9: 9, else 15)."""
+    wmax = 7 if W <= 7 else (9 if W == 9 else 15)
     fit = 64 // (wmax * 4)
     return 8 if fit >= 8 else 4 if fit >= 4 else 2 if fit >= 2 else 1
 
