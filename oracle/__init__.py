@@ -19,6 +19,7 @@ oracle works in physical units instead.
 """
 
 from . import kb, wstack, dft  # noqa: F401
-from .wstack import Params, prepare, wstack_image, wstack_predict, grid_stack, grid_plane, plane_transform  # noqa: F401
+from .wstack import (Params, prepare, wstack_image, wstack_predict, grid_stack, grid_plane, plane_transform,  # noqa: F401
+                     direction_cosines)
 from .dft import dft_image  # noqa: F401
 from ._native import build  # noqa: F401

@@ -22,6 +22,22 @@ It follows the method of Sec. 2 of the paper in its own order:
      xi_j = (j - N/2) / N.
 
 Pixel (i, j): row i carries m_i = (i - N/2) dl, column j carries l_j = (j - N/2) dl.
+
+The w-kernel variant (w_support = Ww >= 3, odd) reads Eq. 3's kernel G(u - u_m, v - v_m,
+w - w_m) with its third argument too: a separable Kaiser-Bessel factor along w, so that each
+visibility is convolved onto its Ww nearest planes instead of going to one.  Steps 3, 5, 7 and 8
+then read:
+  3'. Nw planes with centres w_k = w_c0 + k dw, spaced so that every kept visibility's Ww taps
+      exist: dw = (w_hi - w_lo) / (Nw - Ww), w_c0 = w_lo - h dw (h = (Ww - 1)/2); a visibility
+      sits at plane coordinate z = (w - w_lo) / dw + h (z = h when dw = 0), its first w-tap is
+      k0 = clamp(floor(z + 1/2) - h, 0, Nw - Ww);
+  5'. it adds W_m V_m G_w(k - z) G(q0+a-x) G(p0+b-y) to plane k for k = k0 .. k0 + Ww - 1, with
+      G_w the Kaiser-Bessel kernel of support Ww and shape beta_w (2.34 Ww);
+  7'. the planes are stacked with their phase exp(+2 pi i w_k (n - 1)) as before;
+  8'. the image is also divided by C_w(dw (n_ij - 1)), the w-kernel's Fourier transform: the
+      stacked phase of a visibility is exp(2 pi i w (n - 1)) sum_j G_w(t_j) exp(2 pi i t_j dw (n-1))
+      with t_j the integer-spaced w-tap offsets, and by Poisson's summation formula that sum is
+      C_w(dw (n - 1)) plus aliases C_w(dw (n - 1) + m), m != 0.
 """
 
 from __future__ import annotations
@@ -49,6 +65,12 @@ class Params:
     w_hi: Optional[float] = None
     fold: bool = False              # w-folding: a row with w < 0 is imaged as its conjugate partner
     pad: int = 1                    # grid side = pad * n; the image is the grid image's central n x n
+    w_support: int = 0              # 0: nearest plane; odd >= 3: Kaiser-Bessel kernel across planes
+    beta_w: Optional[float] = None  # the w-kernel's shape (None: 2.34 * w_support)
+
+    @property
+    def wbeta(self) -> float:
+        return 2.34 * self.w_support if self.beta_w is None else float(self.beta_w)
 
     @property
     def n_grid(self) -> int:
@@ -77,6 +99,14 @@ class Prepared:
     dw: float
     sum_w: float
     flip: Optional[np.ndarray] = None   # rows replaced by their conjugate partner (fold)
+    z: Optional[np.ndarray] = None      # w-kernel: plane coordinate of each row (k = first w-tap)
+    w_c0: Optional[float] = None        # centre of plane 0 (w_lo + dw / 2 for the nearest plane)
+
+    def centre(self, k: int) -> float:
+        """Plane k's centre w_k."""
+        if self.z is None:
+            return self.w_lo + (k + 0.5) * self.dw
+        return self.w_c0 + k * self.dw
 
     @property
     def n_kept(self) -> int:
@@ -118,6 +148,23 @@ def prepare(uvw_m: np.ndarray, weights: np.ndarray, freq_hz: float, prm: Params)
             w_lo, w_hi = float(w[sel].min()), float(w[sel].max())
         else:
             w_lo = w_hi = 0.0
+    sum_w = float(wt[keep].sum())
+    if prm.w_support:
+        # step 3': planes spaced so that the Ww w-taps of every kept row exist
+        ww = int(prm.w_support)
+        if ww < 3 or ww % 2 == 0 or prm.n_wplanes <= ww:
+            raise ValueError("w_support must be odd, >= 3 and below n_wplanes")
+        hw = (ww - 1) // 2
+        dw = (w_hi - w_lo) / (prm.n_wplanes - ww)
+        w_c0 = w_lo - hw * dw
+        if dw == 0.0:
+            z = np.full(u.shape[0], float(hw))
+        else:
+            with np.errstate(invalid="ignore"):
+                z = (w - w_lo) / dw + hw
+        z = np.where(keep, z, float(hw))
+        k0 = np.clip(np.floor(z + 0.5) - hw, 0, prm.n_wplanes - ww).astype(np.int64)
+        return Prepared(u, v, w, x, y, q0, p0, keep, k0, w_lo, w_hi, dw, sum_w, flip, z, w_c0)
     dw = (w_hi - w_lo) / prm.n_wplanes
     if dw == 0.0:
         k = np.zeros(u.shape[0], dtype=np.int64)
@@ -126,8 +173,18 @@ def prepare(uvw_m: np.ndarray, weights: np.ndarray, freq_hz: float, prm: Params)
             kf = np.floor((w - w_lo) / dw)
         kf = np.where(keep, kf, 0)
         k = np.clip(kf, 0, prm.n_wplanes - 1).astype(np.int64)
-    sum_w = float(wt[keep].sum())
     return Prepared(u, v, w, x, y, q0, p0, keep, k, w_lo, w_hi, dw, sum_w, flip)
+
+
+def plane_rows(pr: Prepared, prm: Params, plane: int):
+    """The kept rows that add to a plane and the factor of each (1, or G_w(plane - z) with the
+    w-kernel: rows whose first w-tap k0 satisfies k0 <= plane < k0 + Ww)."""
+    if pr.z is None:
+        rows = np.nonzero(pr.keep & (pr.k == plane))[0]
+        return rows, np.ones(rows.size)
+    ww = int(prm.w_support)
+    rows = np.nonzero(pr.keep & (pr.k <= plane) & (pr.k + ww > plane))[0]
+    return rows, _kb.kb(plane - pr.z[rows], ww, prm.wbeta)
 
 
 def tap_weights(pr: Prepared, prm: Params, rows: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
@@ -143,7 +200,7 @@ def grid_plane(pr: Prepared, vis: np.ndarray, weights: np.ndarray, prm: Params, 
     """Step 5 for one w-plane: the complex float64 grid [N, N] of Eq. 3."""
     n = prm.n_grid
     grid = np.zeros((n, n, 2), dtype=np.float64)
-    rows = np.nonzero(pr.keep & (pr.k == plane))[0]
+    rows, fac = plane_rows(pr, prm, plane)
     vis = np.asarray(vis)
     wt = np.asarray(weights).astype(np.float64)
     L = _lib()
@@ -152,7 +209,7 @@ def grid_plane(pr: Prepared, vis: np.ndarray, weights: np.ndarray, prm: Params, 
         vr = vis[r].astype(np.complex128)
         if pr.flip is not None:
             vr = np.where(pr.flip[r], np.conj(vr), vr)
-        wv = wt[r] * vr
+        wv = wt[r] * vr * fac[c0:c0 + chunk]
         wv_re = np.ascontiguousarray(wv.real)
         wv_im = np.ascontiguousarray(wv.imag)
         gx, gy = tap_weights(pr, prm, r)
@@ -239,18 +296,18 @@ def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
         """Steps 5-7 over the planes of one group: sum_k P_k exp(+2 pi i w_k (n - 1))."""
         S = np.zeros(shape, dtype=np.complex128)
         for k in group:
-            if not np.any(pr.keep & (pr.k == k)):
+            prow, _ = plane_rows(pr, prm, k)
+            if prow.size == 0:
                 continue
             g = grid_plane(pr, vis, weights, prm, k)
             o = prm.crop
             if pixels is None:
                 P = plane_transform(g)[o:o + n, o:o + n]
             else:
-                sel = pr.keep & (pr.k == k)
-                lo, hi = int(pr.p0[sel].min()), int(pr.p0[sel].max()) + prm.support - 1
+                lo, hi = int(pr.p0[prow].min()), int(pr.p0[prow].max()) + prm.support - 1
                 P = plane_transform(g, (rows + o, cols + o), grid_rows=np.arange(lo, hi + 1))
             del g
-            wk = pr.w_lo + (k + 0.5) * pr.dw
+            wk = pr.centre(k)
             cyc = wk * nm1
             cyc = cyc - np.round(cyc)
             S += P * np.exp(2j * math.pi * cyc)
@@ -270,6 +327,10 @@ def wstack_image(uvw_m, vis, weights, freq_hz: float, prm: Params,
     xi_j = (cols - n // 2) / prm.n_grid
     xi_i = (rows - n // 2) / prm.n_grid
     corr = np.outer(_kb.kb_taper(xi_i, prm.support, prm.beta), _kb.kb_taper(xi_j, prm.support, prm.beta))
+    if pr.z is not None:
+        # step 8': the w-kernel's transform at dw (n - 1) (a visibility's w-tap weights sum to
+        # about C_w(0), as its uv taps to C(0): dividing by C_w keeps the scale of a unit weight)
+        corr = corr * _kb.kb_taper(pr.dw * nm1, prm.w_support, prm.wbeta)
     D = S / ((pr.sum_w if normalize else 1.0) * corr)
     return D if complex_out else D.real
 
@@ -298,6 +359,8 @@ def wstack_predict(uvw_m, weights, freq_hz: float, prm: Params, image: np.ndarra
     Dropped rows predict 0.  ``weights`` only decide which rows are kept and the plane range
     (as in steps 2-3); they do not scale the prediction.
     """
+    if prm.w_support:
+        raise NotImplementedError("the prediction is the transpose of nearest-plane imaging only")
     n, ng, o = prm.n, prm.n_grid, prm.crop
     pr = prepared if prepared is not None else prepare(uvw_m, weights, freq_hz, prm)
     rows = cols = np.arange(n)

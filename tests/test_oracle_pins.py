@@ -556,3 +556,102 @@ def test_padding_removes_the_edge_aliasing(oracle_mod, c1):
     y = oracle_mod.wstack_predict(sub.uvw_m, ones, sub.freq_hz, prm, X)
     lhs, rhs = float(np.sum(A * X)), float(np.real(np.sum(z * np.conj(y))))
     assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+# ---------------------------------------------------------------------------------------
+# the w-kernel across planes (an accuracy variant): Eq. 3's kernel with its w argument
+
+def _w_alias(oracle, y, Ww, beta_w):
+    """sum_{m != 0} |C_w(y + m)| / |C_w(y)|: the Poisson-sum aliasing of Ww integer-spaced taps."""
+    y = np.asarray(y, dtype=np.float64)
+    ms = np.concatenate([np.arange(-40, 0), np.arange(1, 41)])
+    al = np.abs(oracle.kb.kb_taper(y[..., None] + ms, Ww, beta_w)).sum(-1)
+    return al / np.abs(oracle.kb.kb_taper(y, Ww, beta_w))
+
+
+@pytest.mark.parametrize("Ww", [3, 5, 7])
+def test_wkernel_unit_visibility_carries_the_exact_w_term(oracle_mod, Ww):
+    """P21: one unit visibility at u = v = 0 and w = w0 between plane centres.  Its uv taps give
+    P1's closed-form flat image F(i, j); the w-taps, stacked with the planes' phases and divided
+    by C_w(dw (n - 1)), must give the exact w-term exp(2 pi i w0 (n_ij - 1)) of Eq. 1 up to the
+    Poisson aliasing of the w-taps, sum_{m != 0} |C_w(y + m)| / |C_w(y)| at y = dw (n_ij - 1).
+    A wrong plane centre, w-tap origin, tap sign or correction fails the bound by orders of
+    magnitude."""
+    kbm = oracle_mod.kb
+    n, dl, f, W = 64, 5e-3, 1e9, 7
+    beta, bw = 2.34 * W, 2.34 * Ww
+    nw = Ww + 4
+    w_lo, w_hi = -16.0, 16.0 + 0.37
+    lam = C / f
+    w0 = 5.3
+    uvw = np.array([[0.0, 0.0, w0 * lam]])
+    prm = _prm(oracle_mod, n, dl, nw, W, w_lo=w_lo, w_hi=w_hi)
+    prm.w_support = Ww
+    D = oracle_mod.wstack_image(uvw, np.ones(1), np.ones(1), f, prm, complex_out=True)
+    pr = oracle_mod.prepare(uvw, np.ones(1), f, prm)
+    assert pr.dw == (w_hi - w_lo) / (nw - Ww)
+    t = np.arange(W) - (W - 1) // 2
+    xi = (np.arange(n) - n // 2) / n
+    series = (kbm.kb(t, W, beta)[None, :] * np.cos(2 * math.pi * np.outer(xi, t))).sum(1)
+    flat = np.outer(series / kbm.kb_taper(xi, W, beta), series / kbm.kb_taper(xi, W, beta))
+    _, _, nm1 = oracle_mod.direction_cosines(n, dl, np.arange(n), np.arange(n))
+    exact = np.exp(2j * math.pi * w0 * nm1)
+    y = pr.dw * nm1
+    assert np.max(np.abs(y)) < 0.25
+    dev = np.abs(D / flat - exact)
+    bound = _w_alias(oracle_mod, y, Ww, bw)
+    assert np.all(dev <= 1.05 * bound + 1e-13), float(np.max(dev / (bound + 1e-300)))
+    # and the w-term is really there: without the w-kernel's taps the phase is far off
+    assert np.max(np.abs(exact - 1.0)) > 0.5
+
+
+def test_wkernel_error_falls_at_fixed_nw(oracle_mod, c1):
+    """P22: on the 256^2 plain-method workload at its 8 planes, the w-kernel image is far
+    closer to the direct DFT of Eq. 1 than the nearest-plane image (inner half, where P12's uv
+    aliasing bound is 3.2e-6), the error falls as the w-support grows, and each stays within
+    the w-taps' Poisson aliasing at y = 0 plus that uv bound (support 3 aliases more than the
+    nearest-plane quantisation costs here: its kernel's sidelobes decay slowly)."""
+    ds = c1
+    n = ds.n
+    rows = np.arange(n // 4, 3 * n // 4, 4)
+    cols = np.arange(n // 4 + 1, 3 * n // 4, 4)
+    Dd = oracle_mod.dft_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, n, ds.pixel_rad, pixels=(rows, cols))
+    errs = {}
+    for Ww in (0, 3, 5, 7):
+        prm = _prm(oracle_mod, n, ds.pixel_rad, ds.n_wplanes, ds.support)
+        prm.w_support = Ww
+        Dw = oracle_mod.wstack_image(ds.uvw_m, ds.vis, ds.weights, ds.freq_hz, prm, pixels=(rows, cols))
+        errs[Ww] = np.linalg.norm(Dw - Dd) / np.linalg.norm(Dd)
+    assert errs[7] < errs[5] < errs[3], errs
+    assert errs[5] < 0.1 * errs[0] and errs[7] < 0.01 * errs[0], errs
+    for Ww in (3, 5, 7):
+        assert errs[Ww] < _w_alias(oracle_mod, 0.0, Ww, 2.34 * Ww) + 3.2e-6, (Ww, errs)
+
+
+def test_wkernel_planes_and_taps(oracle_mod):
+    """P23: the plane layout of the w-kernel: every kept row's Ww taps lie on the planes, the
+    data's w range maps to plane coordinates [h, Nw - 1 - h], a row's factors on its planes are
+    the kernel at integer-spaced offsets (they sum to about C_w(0), P10 along w), and a plane
+    receives exactly the rows whose taps reach it."""
+    rng = np.random.default_rng(17)
+    n, dl, f, W, Ww, nw = 64, 2e-3, 1e9, 5, 5, 9
+    uvw = _random_uv(rng, 400, n, dl, f, W, wscale=50.0)
+    prm = _prm(oracle_mod, n, dl, nw, W)
+    prm.w_support = Ww
+    pr = oracle_mod.prepare(uvw, np.ones(400), f, prm)
+    h = (Ww - 1) // 2
+    kept = pr.keep
+    assert np.all(pr.k[kept] >= 0) and np.all(pr.k[kept] + Ww - 1 <= nw - 1)
+    assert abs(pr.z[kept].min() - h) < 1e-9 and abs(pr.z[kept].max() - (nw - 1 - h)) < 1e-9
+    assert np.all(np.abs(pr.k[kept] + h - pr.z[kept]) <= 0.5 + 1e-12)   # nearest plane is the middle tap
+    tot = np.zeros(pr.u.shape[0])
+    for k in range(nw):
+        r, fac = oracle_mod.wstack.plane_rows(pr, prm, k)
+        assert np.array_equal(r, np.nonzero(kept & (pr.k <= k) & (k < pr.k + Ww))[0])
+        tot[r] += fac
+    c0 = oracle_mod.kb.kb_taper(0.0, Ww, 2.34 * Ww)
+    assert np.max(np.abs(tot[kept] / c0 - 1.0)) < 2e-4
+    with pytest.raises(ValueError):
+        bad = _prm(oracle_mod, n, dl, Ww, W)
+        bad.w_support = Ww
+        oracle_mod.prepare(uvw, np.ones(400), f, bad)
