@@ -92,7 +92,15 @@ typedef struct {
     double beta;        /* Kaiser-Bessel shape; <= 0 selects 2.34 * support                */
     double w_lo, w_hi;  /* plane range in wavelengths when WSIMG_FIXED_WRANGE is set       */
     uint32_t flags;
-    uint32_t reserved;  /* must be 0 */
+    uint32_t w_support; /* 0: each visibility goes to its nearest w-plane (Sec. 2).  Odd 3..15
+                           and below n_wplanes: the w-kernel across planes, Eq. 3's kernel with
+                           its w argument: a Kaiser-Bessel kernel of this support along w
+                           (shape 2.34 * w_support) spreads each visibility over that many
+                           neighbouring planes; the planes are spaced
+                           dw = (w_hi - w_lo) / (n_wplanes - w_support) with centres
+                           w_lo + (k - (w_support - 1)/2) dw, and the image is also divided by
+                           the w-kernel's Fourier transform at dw (n_ij - 1).  Not for
+                           wsimg_predict.                                                     */
 } wsimg_params;
 
 typedef struct {

@@ -29,8 +29,8 @@ visibility is convolved onto its Ww nearest planes instead of going to one.  Ste
 then read:
   3'. Nw planes with centres w_k = w_c0 + k dw, spaced so that every kept visibility's Ww taps
       exist: dw = (w_hi - w_lo) / (Nw - Ww), w_c0 = w_lo - h dw (h = (Ww - 1)/2); a visibility
-      sits at plane coordinate z = (w - w_lo) / dw + h (z = h when dw = 0), its first w-tap is
-      k0 = clamp(floor(z + 1/2) - h, 0, Nw - Ww);
+      sits at plane coordinate z = (w - w_lo) / dw + h (z = h when dw = 0; clamped to
+      [h, Nw - 1 - h] for rows outside a fixed range), its first w-tap is k0 = floor(z + 1/2) - h;
   5'. it adds W_m V_m G_w(k - z) G(q0+a-x) G(p0+b-y) to plane k for k = k0 .. k0 + Ww - 1, with
       G_w the Kaiser-Bessel kernel of support Ww and shape beta_w (2.34 Ww);
   7'. the planes are stacked with their phase exp(+2 pi i w_k (n - 1)) as before;
@@ -162,7 +162,9 @@ def prepare(uvw_m: np.ndarray, weights: np.ndarray, freq_hz: float, prm: Params)
         else:
             with np.errstate(invalid="ignore"):
                 z = (w - w_lo) / dw + hw
-        z = np.where(keep, z, float(hw))
+        # rows outside a fixed range are taken at the nearest end of the plane coordinates
+        # (as the nearest-plane method clamps them to the edge planes)
+        z = np.where(keep, np.clip(z, float(hw), float(prm.n_wplanes - 1 - hw)), float(hw))
         k0 = np.clip(np.floor(z + 0.5) - hw, 0, prm.n_wplanes - ww).astype(np.int64)
         return Prepared(u, v, w, x, y, q0, p0, keep, k0, w_lo, w_hi, dw, sum_w, flip, z, w_c0)
     dw = (w_hi - w_lo) / prm.n_wplanes

@@ -41,7 +41,7 @@ def stage_names():
 
 
 def _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad,
-            complex_out=False):
+            complex_out=False, w_support=0):
     p = _lib.Params()
     p.n, p.n_wplanes, p.support = int(n), int(n_wplanes), int(support)
     p.precision = _prec_code(precision)
@@ -61,17 +61,19 @@ def _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normaliz
         p.flags |= _lib.WSIMG_PAD2
     if complex_out:
         p.flags |= _lib.WSIMG_COMPLEX_OUT
+    p.w_support = int(w_support)
     return p
 
 
 def query(n: int, pixel_rad: float, n_wplanes: int, support: int = 7, beta: Optional[float] = None,
           precision: str = "f32", max_vis: int = 0, max_channels: int = 1,
           w_range: Optional[Tuple[float, float]] = None, normalize: bool = True, fold_w: bool = False,
-          pad: int = 1) -> dict:
+          pad: int = 1, w_support: int = 0) -> dict:
     """What a Plan of these arguments would hold (wsimg_plan_query): shapes and device bytes,
     computed on the host without a GPU."""
     L = _lib.load()
-    p = _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad)
+    p = _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad,
+                w_support=w_support)
     i = _lib.PlanInfo()
     _check(L.wsimg_plan_query(ctypes.byref(p), int(max_vis), int(max_channels), ctypes.byref(i)))
     return {f: getattr(i, f) for f, _ in _lib.PlanInfo._fields_}
@@ -91,7 +93,8 @@ class Plan:
     def __init__(self, n: int, pixel_rad: float, n_wplanes: int, support: int = 7,
                  beta: Optional[float] = None, precision: str = "f32", max_vis: int = 0,
                  w_range: Optional[Tuple[float, float]] = None, device=None, max_channels: int = 1,
-                 normalize: bool = True, fold_w: bool = False, pad: int = 1, complex_out: bool = False):
+                 normalize: bool = True, fold_w: bool = False, pad: int = 1, complex_out: bool = False,
+                 w_support: int = 0):
         import torch
 
         self._torch = torch
@@ -100,7 +103,7 @@ class Plan:
         self.precision = "f32" if _prec_code(precision) == _lib.WSIMG_F32 else "f64"
         self.n, self.n_wplanes, self.support = int(n), int(n_wplanes), int(support)
         p = _params(n, pixel_rad, n_wplanes, support, beta, precision, w_range, normalize, fold_w, pad,
-                    complex_out)
+                    complex_out, w_support)
         self.pad = int(pad)
         self.complex_out = bool(complex_out)
         self._L = _lib.load()
@@ -271,14 +274,15 @@ class Plan:
 
 def image(uvw, vis, weights, freq_hz: float, *, n: int, pixel_rad: float, n_wplanes: int,
           support: int = 7, beta: Optional[float] = None, precision: Optional[str] = None,
-          w_range=None, stats: bool = False, complex_out: bool = False):
+          w_range=None, stats: bool = False, complex_out: bool = False, w_support: int = 0):
     """One-shot dirty image (creates and frees a plan); complex_out=True returns the complex
-    image S / (sum W C C) instead of its real part."""
+    image S / (sum W C C) instead of its real part; w_support > 0 spreads each visibility over
+    that many w-planes with a Kaiser-Bessel kernel along w."""
     import torch
     if precision is None:
         precision = "f64" if vis.dtype == torch.complex128 else "f32"
     with Plan(n, pixel_rad, n_wplanes, support, beta, precision, max_vis=uvw.shape[0],
-              w_range=w_range, device=uvw.device, complex_out=complex_out) as p:
+              w_range=w_range, device=uvw.device, complex_out=complex_out, w_support=w_support) as p:
         return p.image(uvw, vis, weights, freq_hz, stats=stats)
 
 
@@ -317,13 +321,13 @@ def image_noalloc(uvw, vis, weights, freq_hz: float, out, *, n: int, pixel_rad: 
 
 def grid(uvw, vis, weights, freq_hz: float, *, n: int, pixel_rad: float, n_wplanes: int,
          support: int = 7, beta: Optional[float] = None, precision: Optional[str] = None,
-         w_range=None, stats: bool = False):
+         w_range=None, stats: bool = False, w_support: int = 0):
     """One-shot gridding step (creates and frees a plan)."""
     import torch
     if precision is None:
         precision = "f64" if vis.dtype == torch.complex128 else "f32"
     with Plan(n, pixel_rad, n_wplanes, support, beta, precision, max_vis=uvw.shape[0],
-              w_range=w_range, device=uvw.device) as p:
+              w_range=w_range, device=uvw.device, w_support=w_support) as p:
         return p.grid(uvw, vis, weights, freq_hz, stats=stats)
 
 

@@ -37,7 +37,7 @@ class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_wplanes", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("pixel_rad", ctypes.c_double), ("beta", ctypes.c_double),
                 ("w_lo", ctypes.c_double), ("w_hi", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("w_support", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):

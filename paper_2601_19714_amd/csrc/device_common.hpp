@@ -92,6 +92,41 @@ __device__ __forceinline__ int plane_index(double w, double w_lo, double dw, int
     return (int)kf;
 }
 
+// The w-kernel across planes (support Ww = 2h + 1): a kept row's plane coordinate
+// z = (w - w_lo) / dw + h, clamped to [h, nw - 1 - h] (h when dw = 0), its first w-tap plane
+// k0 = floor(z + 1/2) - h and its offset f = z - (k0 + h) in [-1/2, 1/2): the row adds to
+// planes k0 .. k0 + Ww - 1 with weights G_w(k - z) = tap (k - k0) of the w-kernel at f.
+struct WTap {
+    int k0;
+    double f;
+};
+__device__ __forceinline__ WTap w_taps(double w, double w_lo, double dw, int nw, int h) {
+#pragma clang fp contract(off)
+    double z = (dw == 0.0) ? (double)h : (w - w_lo) / dw + (double)h;
+    const double zlo = (double)h, zhi = (double)(nw - 1 - h);
+    if (!(z >= zlo)) z = zlo;
+    if (z > zhi) z = zhi;
+    const double c = floor(z + 0.5);
+    WTap t;
+    t.k0 = (int)c - h;
+    t.f = z - c;
+    return t;
+}
+
+// C(xi) = (W / I0(beta)) sinh(r) / r with r = sqrt(beta^2 - (pi W xi)^2) (sin(r) / r when
+// pi W |xi| > beta): the continuous Fourier transform of the Kaiser-Bessel kernel; scale is
+// W / I0(beta).  Float64.
+__device__ __forceinline__ double kb_transform(double xi, int W, double beta, double scale) {
+    const double pw = 3.14159265358979323846 * (double)W * xi;
+    const double a2 = beta * beta - pw * pw;
+    const double r = sqrt(fabs(a2));
+    double s;
+    if (r < 1e-4) s = 1.0 + (a2 > 0.0 ? 1.0 : -1.0) * (r * r / 6.0);
+    else if (a2 > 0.0) s = sinh(r) / r;
+    else s = sin(r) / r;
+    return scale * s;
+}
+
 // sin(2 pi t) and cos(2 pi t) for |t| <= 1/2 (t in turns), float64.  Quadrant reduction
 // q = rint(4t), r = t - q/4 (exact), |r| <= 1/8; then the Taylor series of sin and cos of
 // 2 pi r to degree 21 / 22 (truncation below 5e-16) and the quadrant rotation.

@@ -87,6 +87,7 @@ struct wsimg_plan {
     uint32_t* rec_idx = nullptr;   // input row of each record (prediction)
     void *rec = nullptr, *rec2 = nullptr, *inter = nullptr;   // records by bucket; by (bucket, origin)
     void *tw = nullptr, *inv_taper = nullptr, *kbc = nullptr;
+    void *kbw = nullptr, *rec_w = nullptr, *rec_w2 = nullptr;   // w-kernel: polynomials, row offsets
     int64_t device_bytes = 0;
     std::vector<void*> allocations;
     // timing
@@ -157,9 +158,12 @@ wsimg_status validate_params(const wsimg_params* p, int64_t max_vis) {
     if (!(2.0 * lmax * lmax < 1.0))
         return fail(WSIMG_E_INVALID, "field too wide: a corner pixel has l^2 + m^2 >= 1");
     if (!std::isfinite(p->beta)) return fail(WSIMG_E_INVALID, "beta must be finite");
-    if (p->reserved != 0 ||
-        (p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED | WSIMG_FOLD_W | WSIMG_PAD2 | WSIMG_COMPLEX_OUT)) != 0)
-        return fail(WSIMG_E_INVALID, "unknown flags or reserved field set");
+    if ((p->flags & ~(WSIMG_FIXED_WRANGE | WSIMG_UNNORMALIZED | WSIMG_FOLD_W | WSIMG_PAD2 | WSIMG_COMPLEX_OUT)) != 0)
+        return fail(WSIMG_E_INVALID, "unknown flags set");
+    if (p->w_support != 0 &&
+        (p->w_support < 3 || p->w_support > (uint32_t)kMaxSupport || (p->w_support & 1u) == 0 ||
+         (int64_t)p->w_support >= (int64_t)p->n_wplanes))
+        return fail(WSIMG_E_INVALID, "w_support must be 0, or odd in [3, 15] and below n_wplanes");
     if ((p->flags & WSIMG_PAD2) && p->n > 4096)
         return fail(WSIMG_E_UNSUPPORTED, "a padded grid is at most 8192 cells: n <= 4096 with WSIMG_PAD2");
     if (p->flags & WSIMG_FIXED_WRANGE) {
@@ -188,6 +192,12 @@ wsimg_status upload_tables(wsimg_plan* pl) {
     std::vector<C> htw(n);
     for (int i = 0; i < n; ++i) { htw[i].x = (R)tre[i]; htw[i].y = (R)tim[i]; }
     WS_HIP(hipMemcpy(pl->kbc, hc.data(), hc.size() * sizeof(R), hipMemcpyHostToDevice));
+    if (pl->g.wsup) {      // the w-kernel's tap polynomials
+        std::vector<host::ld> cw = host::kb_tap_polynomials((int)pl->g.wsup, (host::ld)pl->g.wbeta, deg);
+        std::vector<R> hw(cw.size());
+        for (size_t i = 0; i < cw.size(); ++i) hw[i] = (R)cw[i];
+        WS_HIP(hipMemcpy(pl->kbw, hw.data(), hw.size() * sizeof(R), hipMemcpyHostToDevice));
+    }
     WS_HIP(hipMemcpy(pl->inv_taper, ht.data(), ht.size() * sizeof(R), hipMemcpyHostToDevice));
     WS_HIP(hipMemcpy(pl->tw, htw.data(), htw.size() * sizeof(C), hipMemcpyHostToDevice));
     return WSIMG_OK;
@@ -266,15 +276,16 @@ wsimg_status launch_grid_w(wsimg_plan* pl, int nch, bool fft, void* out) {
     const Geom g = pl->g;
     const uint32_t* rc = origin_sorted<R>() ? pl->rec_cell2 : pl->rec_cell;
     const void* rr = origin_sorted<R>() ? pl->rec2 : pl->rec;
+    const R* recw = g.wsup ? (const R*)(origin_sorted<R>() ? pl->rec_w2 : pl->rec_w) : nullptr;
     if (fft) {
         hipLaunchKernelGGL((k_grid_rows<R, LOG2N, WMAX>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1),
                            pl->lds1, pl->stream, g, pl->worklist, pl->list, pl->list_aux, pl->list_cap,
                            pl->offsets, rc, rr, (const R*)pl->kbc, (const C*)pl->tw,
-                           (C*)out, pl->split_acc, pl->split_done);
+                           (C*)out, pl->split_acc, pl->split_done, (const R*)pl->kbw, recw);
     } else {
         hipLaunchKernelGGL((k_grid_only<R, LOG2N, WMAX>), dim3((unsigned)(g.nw * g.S), (unsigned)nch),
                            dim3(pl->nt1), pl->lds1, pl->stream, g, pl->offsets, pl->occ, rc,
-                           rr, (const R*)pl->kbc, (C*)out);
+                           rr, (const R*)pl->kbc, (C*)out, (const R*)pl->kbw, recw);
     }
     WS_LAUNCH_CHECK("grid_rows");
     return WSIMG_OK;
@@ -507,7 +518,8 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     // each gridding work-group's share of the call's record visits (a row's taps reach about
     // (W + H - 2) / H + 1 strips)
     const int64_t visits = bt.total * (int64_t)((g.support + g.H - 2) / g.H + 1);
-    const int64_t share = pl->no_split ? int64_t(0x3FFFFFFF)
+    // a strip gridded from several planes' rows (the w-kernel) is not split into parts
+    const int64_t share = (pl->no_split || g.wsup) ? int64_t(0x3FFFFFFF)
                                        : std::max<int64_t>(kMinPart, visits / std::max(1, pl->persist_blocks));
     hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nbk, 256)), dim3(256), 0, s, nch, pl->offsets, g,
                        pl->occ, pl->plane_occ, pl->list, pl->list_aux, pl->list_cap,
@@ -518,14 +530,16 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     if (M > 0) {
         hipLaunchKernelGGL((k_scatter<R, R>), dim3(blocks_for(M, kScatterThreads), nch), dim3(kScatterThreads), 0, s, ch, uvw,
                            (const C*)vis, (const R*)wts, g, pl->key, pl->rank, pl->offsets,
-                           pl->rec_cell, pl->rec, predict ? pl->rec_idx : nullptr);
+                           pl->rec_cell, pl->rec, predict ? pl->rec_idx : nullptr, pl->scalars,
+                           g.wsup ? (R*)pl->rec_w : nullptr);
         WS_LAUNCH_CHECK("scatter");
     }
     if (auto r = st.after(4)) return r;
 
     if (M > 0 && !predict && origin_sorted<R>()) {
         hipLaunchKernelGGL((k_origin_sort<R>), dim3((unsigned)pl->nb, nch), dim3(kSortThreads), 0, s, g,
-                           pl->offsets, pl->rec_cell, (const void*)pl->rec, pl->rec_cell2, pl->rec2);
+                           pl->offsets, pl->rec_cell, (const void*)pl->rec, pl->rec_cell2, pl->rec2,
+                           g.wsup ? (const R*)pl->rec_w : nullptr, g.wsup ? (R*)pl->rec_w2 : nullptr);
         WS_LAUNCH_CHECK("origin_sort");
     }
     if (auto r = st.after(5)) return r;
@@ -614,6 +628,8 @@ wsimg_status dispatch_predict(wsimg_plan* pl, int64_t n_vis, const double* uvw, 
     if (!image) return fail(WSIMG_E_INVALID, "image pointer is NULL");
     if (pl->p.flags & WSIMG_COMPLEX_OUT)
         return fail(WSIMG_E_INVALID, "wsimg_predict takes a real image: the plan has WSIMG_COMPLEX_OUT");
+    if (pl->g.wsup)
+        return fail(WSIMG_E_UNSUPPORTED, "wsimg_predict is the transpose of nearest-plane imaging (w_support 0)");
     if (stats && capturing(pl)) return fail(WSIMG_E_INVALID, "stats need a host wait: not under graph capture");
     WS_HIP(hipSetDevice(pl->device));
     wsimg_status r = pl->p.precision == WSIMG_F32 ? run_predict<float>(pl, bt, uvw, wts, image, vis_out)
@@ -653,6 +669,10 @@ wsimg_status plan_geometry(wsimg_plan* pl, const wsimg_params* p, int64_t max_vi
     g.fixed_range = (p->flags & WSIMG_FIXED_WRANGE) ? 1 : 0;
     g.unnormalized = (p->flags & WSIMG_UNNORMALIZED) ? 1 : 0;
     g.fold_w = (p->flags & WSIMG_FOLD_W) ? 1 : 0;
+    g.wsup = (int)p->w_support;
+    g.whalf = g.wsup ? (g.wsup - 1) / 2 : 0;
+    g.wbeta = 2.34 * g.wsup;
+    g.wscale = g.wsup ? (double)((host::ld)g.wsup / host::bessel_i0((host::ld)g.wbeta)) : 0.0;
     g.w_lo_fixed = p->w_lo; g.w_hi_fixed = p->w_hi;
     if (auto r = f32 ? shape_of<float>(pl) : shape_of<double>(pl)) return r;
     pl->nb = (int64_t)g.nw * g.S;
@@ -706,6 +726,10 @@ wsimg_status for_each_allocation(wsimg_plan* pl, F&& f) {
     WS_ALLOC(tw, pl->cbytes * g.n, "twiddles");
     WS_ALLOC(inv_taper, pl->rbytes * g.n_img, "taper");
     WS_ALLOC(kbc, pl->rbytes * (size_t)pl->p.support * 17, "kernel polynomials");
+    const bool wk = g.wsup != 0;
+    WS_ALLOC(kbw, wk ? pl->rbytes * (size_t)g.wsup * 17 : 256, "w-kernel polynomials");
+    WS_ALLOC(rec_w, wk ? pl->rbytes * rows : 256, "record w-offsets");
+    WS_ALLOC(rec_w2, (wk && sorted2) ? pl->rbytes * rows : 256, "record w-offsets by origin");
 #undef WS_ALLOC
     return r;
 }
@@ -807,7 +831,7 @@ StaticScratch g_scratch[kMaxDevices];
 // The table key of a plan: every quantity upload_tables reads.
 void table_key(const wsimg_plan* pl, double key[6]) {
     key[0] = pl->p.precision; key[1] = pl->g.n; key[2] = pl->g.n_img; key[3] = pl->p.support;
-    key[4] = pl->p.beta; key[5] = 1.0;
+    key[4] = pl->p.beta; key[5] = 1.0 + pl->g.wsup;
 }
 
 template <typename R>
@@ -828,7 +852,9 @@ wsimg_status image_noalloc(const wsimg_params* p, int64_t n_vis, const double* u
     pl.no_split = true;
     pl.stream = (hipStream_t)hip_stream;
     // sizes first (host arithmetic): the tables at the start of the array, the rest after them
-    auto is_table = [&pl](void** field) { return field == &pl.tw || field == &pl.inv_taper || field == &pl.kbc; };
+    auto is_table = [&pl](void** field) {
+        return field == &pl.tw || field == &pl.inv_taper || field == &pl.kbc || field == &pl.kbw;
+    };
     size_t tab_need = 0, need = kStaticTableBytes;
     for_each_allocation(&pl, [&](void** field, size_t b, const char*) {
         (is_table(field) ? tab_need : need) += (std::max<size_t>(b, 256) + 255) & ~size_t(255);

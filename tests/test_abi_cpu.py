@@ -60,7 +60,8 @@ def _params(mod, **kw):
     ("n", 100), ("n", 8), ("n", 32768), ("n_wplanes", 0), ("n_wplanes", 5000),
     ("support", 8), ("support", 1), ("support", 17), ("precision", 3),
     ("pixel_rad", 0.0), ("pixel_rad", float("nan")), ("pixel_rad", 0.01),
-    ("beta", float("inf")), ("reserved", 1), ("flags", 0x20),
+    ("beta", float("inf")), ("w_support", 1), ("w_support", 4), ("w_support", 17), ("w_support", 9),
+    ("flags", 0x20),
 ])
 def test_invalid_params_rejected_on_host(lib, field, value):
     L, mod = lib
@@ -96,6 +97,16 @@ def test_noalloc_capacity_checked_on_host(lib):
     assert L.wsimg_image_noalloc(ctypes.byref(p), -1, None, None, None, 1e9, None, None, None) == mod.WSIMG_E_INVALID
     # within the array, a missing output is an argument error (still before any device work)
     assert L.wsimg_image_noalloc(ctypes.byref(p), 0, None, None, None, 1e9, None, None, None) == mod.WSIMG_E_INVALID
+
+
+def test_w_support_accepted_below_the_plane_count(lib):
+    """The w-kernel needs an odd support below n_wplanes (8 planes here): 3..7 pass the host
+    checks, 9 does not (the invalid-parameter test above)."""
+    L, mod = lib
+    for ws in (3, 5, 7):
+        p = _params(mod, w_support=ws)
+        info = mod.PlanInfo()
+        assert L.wsimg_plan_query(ctypes.byref(p), 100, 1, ctypes.byref(info)) == mod.WSIMG_OK, ws
 
 
 def test_fixed_range_and_capacity_rules(lib):
