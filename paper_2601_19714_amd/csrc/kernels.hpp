@@ -67,6 +67,7 @@ struct Scalars {
 // of strips split into parts (below).
 struct WorkList {
     unsigned int n_heavy, n_light, next, n_split;
+    unsigned int xnext[8];      // per-XCD counters over the light entries (fetch_item)
 };
 
 // Heavy strips are split.  With `share` the record visits of the call over the gridding
@@ -246,7 +247,7 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
         r.n_occ = 0;
         r.n_planes = 0;
         sc[c] = r;
-        if (c == 0) *wl = WorkList{0u, 0u, 0u, 0u};
+        if (c == 0) *wl = WorkList{0u, 0u, 0u, 0u, {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u}};
     }
 }
 
@@ -430,501 +431,505 @@ k_occupancy(int nch, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __re
         // the planes whose rows reach plane k: k itself, or k - Ww + 1 .. k with the w-kernel
         const int klo = g.wsup ? (k - g.wsup + 1 < 0 ? 0 : k - g.wsup + 1) : k;
         for (int kk = klo; kk <= k; ++kk) {
-                const int base = c * g.nb1 + kk * g.S;
-                visits += offsets[(size_t)(base + sidx + 1) << kLogReplicas] - offsets[(size_t)(base + slo) << kLogReplicas];
-                if (sidx == 0)
-                    po |= offsets[(size_t)(base + g.S) << kLogReplicas] > offsets[(size_t)base << kLogReplicas] ? 1u : 0u;
-            }
-            o = visits > 0 ? 1u : 0u;
-            occ[b] = (uint8_t)o;
-            if (sidx == 0) plane_occ[c * g.nw + k] = (uint8_t)po;
+            const int base = c * g.nb1 + kk * g.S;
+            visits += offsets[(size_t)(base + sidx + 1) << kLogReplicas] - offsets[(size_t)(base + slo) << kLogReplicas];
+            if (sidx == 0)
+                po |= offsets[(size_t)(base + g.S) << kLogReplicas] > offsets[(size_t)base << kLogReplicas] ? 1u : 0u;
         }
-        const int lane = threadIdx.x & 63;
-        const unsigned long long light = __ballot(o && visits <= kHeavyStrip);
-        const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        uint32_t lbase = 0;
-        if (lane == 0 && light) lbase = atomicAdd(&wl->n_light, (unsigned)__popcll(light));
-        lbase = __shfl(lbase, 0, 64);
-        if (o && visits <= kHeavyStrip) {
-            const uint32_t at = list_cap - 1 - (lbase + __popcll(light & below));
-            list[at] = (uint32_t)b;
-            list_aux[at] = 1u;
-        } else if (o) {
-            // heavy: one entry, or one per part when split (heavy strips are few: one atomic each)
-            uint32_t parts = 1, slot = 0;
-            if (visits > 2 * share) {
-                slot = atomicAdd(&wl->n_split, 1u);
-                if (slot < kMaxSplit) {
-                    parts = (visits + share - 1) / share;
-                    parts = parts > kMaxParts ? kMaxParts : parts;
-                } else {
-                    slot = 0;
-                }
-            }
-            const uint32_t at = atomicAdd(&wl->n_heavy, parts);
-            for (uint32_t p = 0; p < parts; ++p) {
-                list[at + p] = (uint32_t)b;
-                list_aux[at + p] = (slot << 16) | (p << 8) | parts;
+        o = visits > 0 ? 1u : 0u;
+        occ[b] = (uint8_t)o;
+        if (sidx == 0) plane_occ[c * g.nw + k] = (uint8_t)po;
+    }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long light = __ballot(o && visits <= kHeavyStrip);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t lbase = 0;
+    if (lane == 0 && light) lbase = atomicAdd(&wl->n_light, (unsigned)__popcll(light));
+    lbase = __shfl(lbase, 0, 64);
+    if (o && visits <= kHeavyStrip) {
+        const uint32_t at = list_cap - 1 - (lbase + __popcll(light & below));
+        list[at] = (uint32_t)b;
+        list_aux[at] = 1u;
+    } else if (o) {
+        // heavy: one entry, or one per part when split (heavy strips are few: one atomic each)
+        uint32_t parts = 1, slot = 0;
+        if (visits > 2 * share) {
+            slot = atomicAdd(&wl->n_split, 1u);
+            if (slot < kMaxSplit) {
+                parts = (visits + share - 1) / share;
+                parts = parts > kMaxParts ? kMaxParts : parts;
+            } else {
+                slot = 0;
             }
         }
-        // per-channel counts: one atomic per wave when the wave lies in one channel
-        const int c0 = __shfl(c, 0, 64);
-        if (__all(b >= total || c == c0)) {
-            o = wave_reduce_sum(o);
-            po = wave_reduce_sum(po);
-            if (lane == 0) {
-                if (o) atomicAdd(&sc[c0].n_occ, (unsigned long long)o);
-                if (po) atomicAdd(&sc[c0].n_planes, (unsigned long long)po);
-            }
-        } else {
-            if (o) atomicAdd(&sc[c].n_occ, 1ull);
-            if (po) atomicAdd(&sc[c].n_planes, 1ull);
+        const uint32_t at = atomicAdd(&wl->n_heavy, parts);
+        for (uint32_t p = 0; p < parts; ++p) {
+            list[at + p] = (uint32_t)b;
+            list_aux[at + p] = (slot << 16) | (p << 8) | parts;
         }
     }
-
-    // Sorted records.  float: one 16-byte record per row,
-    //   x: q0 (13 bits) | p0 mod H (5 bits) | low 14 bits of the x offset code,
-    //   y: high 9 bits of the x offset code | y offset code (23 bits),
-    //   z, w: W*V as float2,
-    // where an offset f = x - floor(x + 1/2) in [-1/2, 1/2) is coded as round((f + 1/2) 2^23)
-    // (a resolution of 1.2e-7 cells; the tap weights change by at most ~6e-8 of their peak).
-    // double: rec_cell (q0 | p0 << 16) plus two double2 per row: the offsets, then W*V.
-    constexpr double kFracScale = 8388608.0;   // 2^23
-
-    __device__ __forceinline__ uint32_t frac_code(double f) {
-        int c = __double2int_rn((f + 0.5) * kFracScale);
-        return (uint32_t)(c < 0 ? 0 : (c > 8388607 ? 8388607 : c));
-    }
-
-    // vis may be null (prediction: the records carry positions only, W*V = 0); rec_idx, when not
-    // null, receives each record's input row.
-    // rows per k_scatter block: blocks of 1024 (like k_key's) write the records of a row block's
-    // buckets from one work-group (C2 scatter 0.20 -> 0.18 ms, 64 channels of 1024^2 0.99 -> 0.80 ms)
-    #ifndef WSIMG_SCATTER_THREADS
-    #define WSIMG_SCATTER_THREADS 1024
-    #endif
-    constexpr int kScatterThreads = WSIMG_SCATTER_THREADS;
-    template <typename R, typename WT>
-    __global__ void __launch_bounds__(kScatterThreads)
-    k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __restrict__ vis,
-              const WT* __restrict__ wts, Geom g, const uint32_t* __restrict__ key,
-              const uint32_t* __restrict__ rank, const uint32_t* __restrict__ offsets,
-              uint32_t* __restrict__ rec_cell, void* __restrict__ rec, uint32_t* __restrict__ rec_idx,
-              const Scalars* __restrict__ sc, R* __restrict__ rec_w) {
-        using C = typename Cx<R>::T;
-        const int c = blockIdx.y;
-        const int64_t r0 = ch.row_off[c], r1 = ch.row_off[c + 1];
-        const int64_t m = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (m >= r1) return;
-        const uint32_t kk = key[m];
-        if (kk == 0xFFFFFFFFu) return;
-        const double wt = (double)wts[m];
-        RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support, g.fold_w);
-        const uint32_t rep = row_replica(m - r0);              // the row block's replica (as in k_key)
-        const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + rep] + rank[m];
-        const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
-        // a prediction's records carry no W*V: their value slot holds (1, 0) for a folded row
-        C v = vis ? vis[m] : cmake<C>(rg.flip ? (R)1 : (R)0, (R)0);
-        if (vis && rg.flip) v.y = -v.y;
-        const R w = vis ? (R)wts[m] : (R)1;
-        if (rec_idx) rec_idx[pos] = (uint32_t)m;
-        if (rec_w) rec_w[pos] = (R)w_taps(rg.w, sc[c].w_lo, sc[c].dw, g.nw, g.whalf).f;   // w-kernel offset
-        if constexpr (sizeof(R) == 4) {
-            const uint32_t ux = frac_code(rg.x - rg.cx), uy = frac_code(rg.y - rg.cy);
-            const uint32_t pr = (uint32_t)p0 & (uint32_t)(g.H - 1);
-            uint4 q;
-            q.x = (uint32_t)q0 | (pr << 13) | ((ux & 0x3FFFu) << 18);
-            q.y = (ux >> 14) | (uy << 9);
-            q.z = __float_as_uint(w * v.x);
-            q.w = __float_as_uint(w * v.y);
-            reinterpret_cast<uint4*>(rec)[pos] = q;
-        } else {
-            rec_cell[pos] = (uint32_t)q0 | ((uint32_t)p0 << 16);
-            double2* r2 = reinterpret_cast<double2*>(rec);
-            r2[2 * (size_t)pos] = make_double2(rg.x - rg.cx, rg.y - rg.cy);
-            r2[2 * (size_t)pos + 1] = make_double2(w * v.x, w * v.y);
+    // per-channel counts: one atomic per wave when the wave lies in one channel
+    const int c0 = __shfl(c, 0, 64);
+    if (__all(b >= total || c == c0)) {
+        o = wave_reduce_sum(o);
+        po = wave_reduce_sum(po);
+        if (lane == 0) {
+            if (o) atomicAdd(&sc[c0].n_occ, (unsigned long long)o);
+            if (po) atomicAdd(&sc[c0].n_planes, (unsigned long long)po);
         }
+    } else {
+        if (o) atomicAdd(&sc[c].n_occ, 1ull);
+        if (po) atomicAdd(&sc[c].n_planes, 1ull);
     }
+}
 
-    // One record as stored.
-    template <typename R> struct RawRec;
-    template <> struct RawRec<float> { uint4 q; };
-    template <> struct RawRec<double> { uint32_t cell; double2 f, v; };
+// Sorted records.  float: one 16-byte record per row,
+//   x: q0 (13 bits) | p0 mod H (5 bits) | low 14 bits of the x offset code,
+//   y: high 9 bits of the x offset code | y offset code (23 bits),
+//   z, w: W*V as float2,
+// where an offset f = x - floor(x + 1/2) in [-1/2, 1/2) is coded as round((f + 1/2) 2^23)
+// (a resolution of 1.2e-7 cells; the tap weights change by at most ~6e-8 of their peak).
+// double: rec_cell (q0 | p0 << 16) plus two double2 per row: the offsets, then W*V.
+constexpr double kFracScale = 8388608.0;   // 2^23
 
-    template <typename R>
-    __device__ __forceinline__ RawRec<R> fetch_record(const uint32_t* __restrict__ rec_cell,
-                                                      const void* __restrict__ rec, uint32_t r) {
-        RawRec<R> x;
-        if constexpr (sizeof(R) == 4) {
-            x.q = reinterpret_cast<const uint4*>(rec)[r];
-        } else {
-            x.cell = rec_cell[r];
-            const double2* r2 = reinterpret_cast<const double2*>(rec);
-            x.f = r2[2 * (size_t)r];
-            x.v = r2[2 * (size_t)r + 1];
+__device__ __forceinline__ uint32_t frac_code(double f) {
+    int c = __double2int_rn((f + 0.5) * kFracScale);
+    return (uint32_t)(c < 0 ? 0 : (c > 8388607 ? 8388607 : c));
+}
+
+// vis may be null (prediction: the records carry positions only, W*V = 0); rec_idx, when not
+// null, receives each record's input row.
+// rows per k_scatter block: blocks of 1024 (like k_key's) write the records of a row block's
+// buckets from one work-group (C2 scatter 0.20 -> 0.18 ms, 64 channels of 1024^2 0.99 -> 0.80 ms)
+#ifndef WSIMG_SCATTER_THREADS
+#define WSIMG_SCATTER_THREADS 1024
+#endif
+constexpr int kScatterThreads = WSIMG_SCATTER_THREADS;
+template <typename R, typename WT>
+__global__ void __launch_bounds__(kScatterThreads)
+k_scatter(Chan ch, const double* __restrict__ uvw, const typename Cx<R>::T* __restrict__ vis,
+          const WT* __restrict__ wts, Geom g, const uint32_t* __restrict__ key,
+          const uint32_t* __restrict__ rank, const uint32_t* __restrict__ offsets,
+          uint32_t* __restrict__ rec_cell, void* __restrict__ rec, uint32_t* __restrict__ rec_idx,
+          const Scalars* __restrict__ sc, R* __restrict__ rec_w) {
+    using C = typename Cx<R>::T;
+    const int c = blockIdx.y;
+    const int64_t r0 = ch.row_off[c], r1 = ch.row_off[c + 1];
+    const int64_t m = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= r1) return;
+    const uint32_t kk = key[m];
+    if (kk == 0xFFFFFFFFu) return;
+    const double wt = (double)wts[m];
+    RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support, g.fold_w);
+    const uint32_t rep = row_replica(m - r0);              // the row block's replica (as in k_key)
+    const uint32_t pos = offsets[((size_t)kk << kLogReplicas) + rep] + rank[m];
+    const int q0 = (int)rg.cx - g.half, p0 = (int)rg.cy - g.half;
+    // a prediction's records carry no W*V: their value slot holds (1, 0) for a folded row
+    C v = vis ? vis[m] : cmake<C>(rg.flip ? (R)1 : (R)0, (R)0);
+    if (vis && rg.flip) v.y = -v.y;
+    const R w = vis ? (R)wts[m] : (R)1;
+    if (rec_idx) rec_idx[pos] = (uint32_t)m;
+    if (rec_w) rec_w[pos] = (R)w_taps(rg.w, sc[c].w_lo, sc[c].dw, g.nw, g.whalf).f;   // w-kernel offset
+    if constexpr (sizeof(R) == 4) {
+        const uint32_t ux = frac_code(rg.x - rg.cx), uy = frac_code(rg.y - rg.cy);
+        const uint32_t pr = (uint32_t)p0 & (uint32_t)(g.H - 1);
+        uint4 q;
+        q.x = (uint32_t)q0 | (pr << 13) | ((ux & 0x3FFFu) << 18);
+        q.y = (ux >> 14) | (uy << 9);
+        q.z = __float_as_uint(w * v.x);
+        q.w = __float_as_uint(w * v.y);
+        reinterpret_cast<uint4*>(rec)[pos] = q;
+    } else {
+        rec_cell[pos] = (uint32_t)q0 | ((uint32_t)p0 << 16);
+        double2* r2 = reinterpret_cast<double2*>(rec);
+        r2[2 * (size_t)pos] = make_double2(rg.x - rg.cx, rg.y - rg.cy);
+        r2[2 * (size_t)pos + 1] = make_double2(w * v.x, w * v.y);
+    }
+}
+
+// One record as stored.
+template <typename R> struct RawRec;
+template <> struct RawRec<float> { uint4 q; };
+template <> struct RawRec<double> { uint32_t cell; double2 f, v; };
+
+template <typename R>
+__device__ __forceinline__ RawRec<R> fetch_record(const uint32_t* __restrict__ rec_cell,
+                                                  const void* __restrict__ rec, uint32_t r) {
+    RawRec<R> x;
+    if constexpr (sizeof(R) == 4) {
+        x.q = reinterpret_cast<const uint4*>(rec)[r];
+    } else {
+        x.cell = rec_cell[r];
+        const double2* r2 = reinterpret_cast<const double2*>(rec);
+        x.f = r2[2 * (size_t)r];
+        x.v = r2[2 * (size_t)r + 1];
+    }
+    return x;
+}
+
+template <typename R>
+__device__ __forceinline__ void store_record(uint32_t* __restrict__ rec_cell, void* __restrict__ rec,
+                                             uint32_t r, const RawRec<R>& x) {
+    if constexpr (sizeof(R) == 4) {
+        reinterpret_cast<uint4*>(rec)[r] = x.q;
+    } else {
+        rec_cell[r] = x.cell;
+        double2* r2 = reinterpret_cast<double2*>(rec);
+        r2[2 * (size_t)r] = x.f;
+        r2[2 * (size_t)r + 1] = x.v;
+    }
+}
+
+// Tap origin (q0, p0), sub-cell offsets and W*V in the plan precision; strip is the strip of
+// the record's bucket (the float record keeps only p0 mod H).
+template <typename R>
+__device__ __forceinline__ void decode_record(const RawRec<R>& x, int strip, int log2H, int& q0, int& p0,
+                                              typename Cx<R>::T& fr, typename Cx<R>::T& v) {
+    using C = typename Cx<R>::T;
+    if constexpr (sizeof(R) == 4) {
+        const uint4 q = x.q;
+        q0 = (int)(q.x & 0x1FFFu);
+        p0 = (strip << log2H) + (int)((q.x >> 13) & 0x1Fu);
+        const uint32_t ux = (q.x >> 18) | ((q.y & 0x1FFu) << 14), uy = q.y >> 9;
+        const float inv = 1.0f / 8388608.0f;
+        fr = cmake<C>((float)ux * inv - 0.5f, (float)uy * inv - 0.5f);
+        v = cmake<C>(__uint_as_float(q.z), __uint_as_float(q.w));
+    } else {
+        q0 = (int)(x.cell & 0xFFFFu);
+        p0 = (int)(x.cell >> 16);
+        fr = x.f;
+        v = x.v;
+    }
+}
+
+// Origin index q0 * H + (p0 mod H) of a stored record (< H * N <= 8192).
+template <typename R>
+__device__ __forceinline__ uint32_t raw_origin(const RawRec<R>& x, int log2H) {
+    if constexpr (sizeof(R) == 4) return ((x.q.x & 0x1FFFu) << log2H) | ((x.q.x >> 13) & 0x1Fu);
+    else return ((x.cell & 0xFFFFu) << log2H) | ((x.cell >> 16) & ((1u << log2H) - 1u));
+}
+
+// ---------------------------------------------------------------------------------------
+// Records of each bucket grouped by tap origin.
+//
+// Inside one bucket (channel, plane, strip) the records are put in order of their tap origin
+// o = q0 * H + (p0 mod H), o < H * N <= 8192, by a counting sort in LDS (one work-group per
+// bucket).  Records with the same origin then lie next to each other, and the gridding sums
+// a run of them in registers before adding it to the strip once: on 8 s integrations a
+// baseline stays in one grid cell for several steps, and dense buckets hold tens of records
+// per origin.
+constexpr int kOriginBins = 8192;
+constexpr int kSortThreads = 512;
+
+// Work-group (x, c) = bucket x of channel c.
+template <typename R>
+__global__ void __launch_bounds__(kSortThreads)
+k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
+              const void* __restrict__ rec, uint32_t* __restrict__ rec_cell2, void* __restrict__ rec2,
+              const R* __restrict__ rec_w, R* __restrict__ rec_w2) {
+    __shared__ uint32_t hist[kOriginBins];
+    __shared__ uint32_t part[kSortThreads / 64];
+    constexpr int PER = kOriginBins / kSortThreads;
+    const size_t b = (size_t)blockIdx.y * g.nb1 + blockIdx.x;
+    const uint32_t beg = offsets[b << kLogReplicas], end = offsets[(b + 1) << kLogReplicas];
+    const int t = threadIdx.x;
+    if (end - beg <= 1) {
+        if (end - beg == 1 && t == 0) {
+            store_record<R>(rec_cell2, rec2, beg, fetch_record<R>(rec_cell, rec, beg));
+            if (rec_w) rec_w2[beg] = rec_w[beg];
         }
-        return x;
+        return;
     }
-
-    template <typename R>
-    __device__ __forceinline__ void store_record(uint32_t* __restrict__ rec_cell, void* __restrict__ rec,
-                                                 uint32_t r, const RawRec<R>& x) {
-        if constexpr (sizeof(R) == 4) {
-            reinterpret_cast<uint4*>(rec)[r] = x.q;
-        } else {
-            rec_cell[r] = x.cell;
-            double2* r2 = reinterpret_cast<double2*>(rec);
-            r2[2 * (size_t)r] = x.f;
-            r2[2 * (size_t)r + 1] = x.v;
-        }
-    }
-
-    // Tap origin (q0, p0), sub-cell offsets and W*V in the plan precision; strip is the strip of
-    // the record's bucket (the float record keeps only p0 mod H).
-    template <typename R>
-    __device__ __forceinline__ void decode_record(const RawRec<R>& x, int strip, int log2H, int& q0, int& p0,
-                                                  typename Cx<R>::T& fr, typename Cx<R>::T& v) {
-        using C = typename Cx<R>::T;
-        if constexpr (sizeof(R) == 4) {
-            const uint4 q = x.q;
-            q0 = (int)(q.x & 0x1FFFu);
-            p0 = (strip << log2H) + (int)((q.x >> 13) & 0x1Fu);
-            const uint32_t ux = (q.x >> 18) | ((q.y & 0x1FFu) << 14), uy = q.y >> 9;
-            const float inv = 1.0f / 8388608.0f;
-            fr = cmake<C>((float)ux * inv - 0.5f, (float)uy * inv - 0.5f);
-            v = cmake<C>(__uint_as_float(q.z), __uint_as_float(q.w));
-        } else {
-            q0 = (int)(x.cell & 0xFFFFu);
-            p0 = (int)(x.cell >> 16);
-            fr = x.f;
-            v = x.v;
-        }
-    }
-
-    // Origin index q0 * H + (p0 mod H) of a stored record (< H * N <= 8192).
-    template <typename R>
-    __device__ __forceinline__ uint32_t raw_origin(const RawRec<R>& x, int log2H) {
-        if constexpr (sizeof(R) == 4) return ((x.q.x & 0x1FFFu) << log2H) | ((x.q.x >> 13) & 0x1Fu);
-        else return ((x.cell & 0xFFFFu) << log2H) | ((x.cell >> 16) & ((1u << log2H) - 1u));
-    }
-
-    // ---------------------------------------------------------------------------------------
-    // Records of each bucket grouped by tap origin.
-    //
-    // Inside one bucket (channel, plane, strip) the records are put in order of their tap origin
-    // o = q0 * H + (p0 mod H), o < H * N <= 8192, by a counting sort in LDS (one work-group per
-    // bucket).  Records with the same origin then lie next to each other, and the gridding sums
-    // a run of them in registers before adding it to the strip once: on 8 s integrations a
-    // baseline stays in one grid cell for several steps, and dense buckets hold tens of records
-    // per origin.
-    constexpr int kOriginBins = 8192;
-    constexpr int kSortThreads = 512;
-
-    // Work-group (x, c) = bucket x of channel c.
-    template <typename R>
-    __global__ void __launch_bounds__(kSortThreads)
-    k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
-                  const void* __restrict__ rec, uint32_t* __restrict__ rec_cell2, void* __restrict__ rec2,
-                  const R* __restrict__ rec_w, R* __restrict__ rec_w2) {
-        __shared__ uint32_t hist[kOriginBins];
-        __shared__ uint32_t part[kSortThreads / 64];
-        constexpr int PER = kOriginBins / kSortThreads;
-        const size_t b = (size_t)blockIdx.y * g.nb1 + blockIdx.x;
-        const uint32_t beg = offsets[b << kLogReplicas], end = offsets[(b + 1) << kLogReplicas];
-        const int t = threadIdx.x;
-        if (end - beg <= 1) {
-            if (end - beg == 1 && t == 0) {
-                store_record<R>(rec_cell2, rec2, beg, fetch_record<R>(rec_cell, rec, beg));
-                if (rec_w) rec_w2[beg] = rec_w[beg];
-            }
-            return;
-        }
 #pragma unroll
-        for (int i = 0; i < PER; ++i) hist[i * kSortThreads + t] = 0u;
-        __syncthreads();
-        for (uint32_t r = beg + t; r < end; r += kSortThreads)
-            atomicAdd(&hist[raw_origin<R>(fetch_record<R>(rec_cell, rec, r), g.log2H)], 1u);
-        __syncthreads();
-        // exclusive scan of the bins: thread t owns bins [t * PER, (t + 1) * PER); the thread sums
-        // are scanned within each wave by shuffles, then the wave totals are added across waves
-        uint32_t v[PER], sum = 0;
+    for (int i = 0; i < PER; ++i) hist[i * kSortThreads + t] = 0u;
+    __syncthreads();
+    for (uint32_t r = beg + t; r < end; r += kSortThreads)
+        atomicAdd(&hist[raw_origin<R>(fetch_record<R>(rec_cell, rec, r), g.log2H)], 1u);
+    __syncthreads();
+    // exclusive scan of the bins: thread t owns bins [t * PER, (t + 1) * PER); the thread sums
+    // are scanned within each wave by shuffles, then the wave totals are added across waves
+    uint32_t v[PER], sum = 0;
 #pragma unroll
-        for (int i = 0; i < PER; ++i) { v[i] = hist[t * PER + i]; sum += v[i]; }
-        const int lane = t & 63, wave = t >> 6;
-        uint32_t inc = sum;
+    for (int i = 0; i < PER; ++i) { v[i] = hist[t * PER + i]; sum += v[i]; }
+    const int lane = t & 63, wave = t >> 6;
+    uint32_t inc = sum;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
-        if (lane == 63) part[wave] = inc;
-        __syncthreads();
-        uint32_t run = inc - sum;
-        for (int w = 0; w < wave; ++w) run += part[w];
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) part[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int w = 0; w < wave; ++w) run += part[w];
 #pragma unroll
-        for (int i = 0; i < PER; ++i) { hist[t * PER + i] = run; run += v[i]; }
-        __syncthreads();
-        for (uint32_t r = beg + t; r < end; r += kSortThreads) {
-            const RawRec<R> x = fetch_record<R>(rec_cell, rec, r);
-            const uint32_t to = beg + atomicAdd(&hist[raw_origin<R>(x, g.log2H)], 1u);
-            store_record<R>(rec_cell2, rec2, to, x);
-            if (rec_w) rec_w2[to] = rec_w[r];
-        }
+    for (int i = 0; i < PER; ++i) { hist[t * PER + i] = run; run += v[i]; }
+    __syncthreads();
+    for (uint32_t r = beg + t; r < end; r += kSortThreads) {
+        const RawRec<R> x = fetch_record<R>(rec_cell, rec, r);
+        const uint32_t to = beg + atomicAdd(&hist[raw_origin<R>(x, g.log2H)], 1u);
+        store_record<R>(rec_cell2, rec2, to, x);
+        if (rec_w) rec_w2[to] = rec_w[r];
     }
+}
 
-    // ---------------------------------------------------------------------------------------
-    // Work-group shapes, fixed per (precision, image size).  Each FFT runs on a base radix
-    // 2^LR (2^LR elements per thread between LDS exchanges); the base radix of each pass and
-    // the stacking block sizes are build-time choices (WSIMG_<precision>_LR1/_LR2/_PX2/_BS), picked
-    // by measurement.
-    //   pass 1: H grid rows per strip; the strip accumulates in float64 (16 B per cell) whatever
-    //           the precision, so H * N <= 8192 cells; NT1 = H * N / 2^LR1 threads;
-    //   pass 2: the intermediate's column blocks hold B columns, B * N = PX2 pixels; a stacking
-    //           block takes BS <= B of them with NT2 = BS * N / 2^LR2 threads.
-    #ifndef WSIMG_F32_LR1
-    #define WSIMG_F32_LR1 4
-    #endif
-    // float stacking, per image size (log2 n): radix 16 at 4096^2 (1.16 ms against 1.26 ms with
-    // radix 8 for 32 planes), radix 8 at 8192^2 (64 planes: 12.3 ms against 14.3 ms; 1024 threads of
-    // 8 pixels keep 4 waves per SIMD where 512 threads of 16 pixels kept 2) and below 4096^2
-    // (1024^2: 1.92 ms against 2.18 ms for 64 channels of 16 planes).  WSIMG_F32_LR2_N<log2 n>
-    // sets one size (the autotuner's per-shape choices); WSIMG_F32_LR2 overrides every size.
-    #ifndef WSIMG_F32_LR2_N12
-    #define WSIMG_F32_LR2_N12 4
-    #endif
-    #ifndef WSIMG_F32_LR2_N13
-    #define WSIMG_F32_LR2_N13 3
-    #endif
-    #ifndef WSIMG_F32_LR2_SMALL
-    #define WSIMG_F32_LR2_SMALL 3
-    #endif
-    template <int LOG2N> constexpr int f32_stack_radix_log2() {
-    #ifdef WSIMG_F32_LR2
-        return WSIMG_F32_LR2;
-    #else
-    #ifdef WSIMG_F32_LR2_N4
-        if (LOG2N == 4) return WSIMG_F32_LR2_N4;
-    #endif
-    #ifdef WSIMG_F32_LR2_N5
-        if (LOG2N == 5) return WSIMG_F32_LR2_N5;
-    #endif
-    #ifdef WSIMG_F32_LR2_N6
-        if (LOG2N == 6) return WSIMG_F32_LR2_N6;
-    #endif
-    #ifdef WSIMG_F32_LR2_N7
-        if (LOG2N == 7) return WSIMG_F32_LR2_N7;
-    #endif
-    #ifdef WSIMG_F32_LR2_N8
-        if (LOG2N == 8) return WSIMG_F32_LR2_N8;
-    #endif
-    #ifdef WSIMG_F32_LR2_N9
-        if (LOG2N == 9) return WSIMG_F32_LR2_N9;
-    #endif
-    #ifdef WSIMG_F32_LR2_N10
-        if (LOG2N == 10) return WSIMG_F32_LR2_N10;
-    #endif
-    #ifdef WSIMG_F32_LR2_N11
-        if (LOG2N == 11) return WSIMG_F32_LR2_N11;
-    #endif
-        return LOG2N == 13 ? WSIMG_F32_LR2_N13 : (LOG2N == 12 ? WSIMG_F32_LR2_N12 : WSIMG_F32_LR2_SMALL);
-    #endif
-    }
-    // base radix of the prediction's column pass (the stacking pass's transpose)
-    #ifndef WSIMG_F32_LR2A
-    #define WSIMG_F32_LR2A 3
-    #endif
-    #ifndef WSIMG_F64_LR2A
-    #define WSIMG_F64_LR2A 3
-    #endif
-    #ifndef WSIMG_F64_LR1
-    #define WSIMG_F64_LR1 4
-    #endif
-    #ifndef WSIMG_F64_LR2
-    #define WSIMG_F64_LR2 3
-    #endif
-    // cells of one gridding strip (H * N): its float64 accumulator takes 16 B per cell of LDS.
-    // Images below 4096^2 use the smaller strip (two work-groups per CU, fewer walks per strip).
-    #ifndef WSIMG_STRIP_CELLS
-    #define WSIMG_STRIP_CELLS 8192
-    #endif
-    #ifndef WSIMG_STRIP_CELLS_SMALL
-    #define WSIMG_STRIP_CELLS_SMALL 4096
-    #endif
-    // grid rows per strip below 4096^2 when > 0 (instead of STRIP_CELLS_SMALL / N, at most 4).
-    // Two, the walk's register rows for W <= 7, so that a record visit decodes its record once:
-    // 64 channels of 1024^2 10.0 -> 9.45 ms, 256^2 0.51 -> 0.36 ms, 2048^2 unchanged
-    #ifndef WSIMG_STRIP_ROWS_SMALL
-    #define WSIMG_STRIP_ROWS_SMALL 2
-    #endif
-    static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
-                  "origins of a strip index an 8192-bin histogram");
-    #ifndef WSIMG_F32_PX2
-    #define WSIMG_F32_PX2 8192
-    #endif
-    #ifndef WSIMG_F64_PX2
-    #define WSIMG_F64_PX2 4096
-    #endif
-    // Per image size: at 8192^2 a strip is one grid row, and with one column per layout block each
-    // row element went to its own 64 KB-strided address (8-byte stores: 32 GB written for 9.3 GB of
-    // strips on the LOFAR-shaped image).  Eight float columns per block make every row store a
-    // whole 64-byte segment (gridding 28.9 -> 20.8 ms, stacking 12.1 -> 13.9 ms as each stacking
-    // block now reads 8 of every 64 bytes: 47.7 -> 41.4 ms per image; 2, 4 and 16 columns: 45.9,
-    // 43.3, 43.4 ms).  In double, 1, 2, 4 and 8 columns time alike (101-104 ms): one is kept.
-    #ifndef WSIMG_F32_PX2_N13
-    #define WSIMG_F32_PX2_N13 65536
-    #endif
-    #ifndef WSIMG_F64_PX2_N13
-    #define WSIMG_F64_PX2_N13 8192
-    #endif
-    #ifndef WSIMG_F32_PX2_N12
-    #define WSIMG_F32_PX2_N12 WSIMG_F32_PX2
-    #endif
-    #ifndef WSIMG_F64_PX2_N12
-    #define WSIMG_F64_PX2_N12 WSIMG_F64_PX2
-    #endif
-    template <typename R, int LOG2N> constexpr int layout_pixels() {
-        if constexpr (sizeof(R) == 4) return LOG2N == 13 ? WSIMG_F32_PX2_N13 : (LOG2N == 12 ? WSIMG_F32_PX2_N12 : WSIMG_F32_PX2);
-        else return LOG2N == 13 ? WSIMG_F64_PX2_N13 : (LOG2N == 12 ? WSIMG_F64_PX2_N12 : WSIMG_F64_PX2);
-    }
-    // image columns per stacking block (0: all B columns of a layout block).  float: one, so that
-    // several blocks share a CU and one block's barriers overlap another's work (a 4096^2 image
-    // of 32 planes: 1.44 -> 1.26 ms with radix-8 passes, 1.18 ms with radix 16: 256 threads per
-    // block, two blocks per CU)
-    #ifndef WSIMG_F32_BS
-    #define WSIMG_F32_BS 1
-    #endif
-    #ifndef WSIMG_F64_BS
-    #define WSIMG_F64_BS 0
-    #endif
-    // 1: stacking blocks that share layout blocks are placed on one XCD (below)
-    #ifndef WSIMG_COLS_XCD_MAP
-    #define WSIMG_COLS_XCD_MAP 1
-    #endif
-    // column blocks per XCD group (0: one 128-byte line of image pixels per row)
-    #ifndef WSIMG_COLS_XCD_Q
-    #define WSIMG_COLS_XCD_Q 0
-    #endif
+// ---------------------------------------------------------------------------------------
+// Work-group shapes, fixed per (precision, image size).  Each FFT runs on a base radix
+// 2^LR (2^LR elements per thread between LDS exchanges); the base radix of each pass and
+// the stacking block sizes are build-time choices (WSIMG_<precision>_LR1/_LR2/_PX2/_BS), picked
+// by measurement.
+//   pass 1: H grid rows per strip; the strip accumulates in float64 (16 B per cell) whatever
+//           the precision, so H * N <= 8192 cells; NT1 = H * N / 2^LR1 threads;
+//   pass 2: the intermediate's column blocks hold B columns, B * N = PX2 pixels; a stacking
+//           block takes BS <= B of them with NT2 = BS * N / 2^LR2 threads.
+#ifndef WSIMG_F32_LR1
+#define WSIMG_F32_LR1 4
+#endif
+// per image size (log2 n) override of the gridding work-group's row-transform radix
+#ifndef WSIMG_F32_LR1_N13
+#define WSIMG_F32_LR1_N13 WSIMG_F32_LR1
+#endif
+// float stacking, per image size (log2 n): radix 16 at 4096^2 (1.16 ms against 1.26 ms with
+// radix 8 for 32 planes), radix 8 at 8192^2 (64 planes: 12.3 ms against 14.3 ms; 1024 threads of
+// 8 pixels keep 4 waves per SIMD where 512 threads of 16 pixels kept 2) and below 4096^2
+// (1024^2: 1.92 ms against 2.18 ms for 64 channels of 16 planes).  WSIMG_F32_LR2_N<log2 n>
+// sets one size (the autotuner's per-shape choices); WSIMG_F32_LR2 overrides every size.
+#ifndef WSIMG_F32_LR2_N12
+#define WSIMG_F32_LR2_N12 4
+#endif
+#ifndef WSIMG_F32_LR2_N13
+#define WSIMG_F32_LR2_N13 3
+#endif
+#ifndef WSIMG_F32_LR2_SMALL
+#define WSIMG_F32_LR2_SMALL 3
+#endif
+template <int LOG2N> constexpr int f32_stack_radix_log2() {
+#ifdef WSIMG_F32_LR2
+    return WSIMG_F32_LR2;
+#else
+#ifdef WSIMG_F32_LR2_N4
+    if (LOG2N == 4) return WSIMG_F32_LR2_N4;
+#endif
+#ifdef WSIMG_F32_LR2_N5
+    if (LOG2N == 5) return WSIMG_F32_LR2_N5;
+#endif
+#ifdef WSIMG_F32_LR2_N6
+    if (LOG2N == 6) return WSIMG_F32_LR2_N6;
+#endif
+#ifdef WSIMG_F32_LR2_N7
+    if (LOG2N == 7) return WSIMG_F32_LR2_N7;
+#endif
+#ifdef WSIMG_F32_LR2_N8
+    if (LOG2N == 8) return WSIMG_F32_LR2_N8;
+#endif
+#ifdef WSIMG_F32_LR2_N9
+    if (LOG2N == 9) return WSIMG_F32_LR2_N9;
+#endif
+#ifdef WSIMG_F32_LR2_N10
+    if (LOG2N == 10) return WSIMG_F32_LR2_N10;
+#endif
+#ifdef WSIMG_F32_LR2_N11
+    if (LOG2N == 11) return WSIMG_F32_LR2_N11;
+#endif
+    return LOG2N == 13 ? WSIMG_F32_LR2_N13 : (LOG2N == 12 ? WSIMG_F32_LR2_N12 : WSIMG_F32_LR2_SMALL);
+#endif
+}
+// base radix of the prediction's column pass (the stacking pass's transpose)
+#ifndef WSIMG_F32_LR2A
+#define WSIMG_F32_LR2A 3
+#endif
+#ifndef WSIMG_F64_LR2A
+#define WSIMG_F64_LR2A 3
+#endif
+#ifndef WSIMG_F64_LR1
+#define WSIMG_F64_LR1 4
+#endif
+#ifndef WSIMG_F64_LR2
+#define WSIMG_F64_LR2 3
+#endif
+// cells of one gridding strip (H * N): its float64 accumulator takes 16 B per cell of LDS.
+// Images below 4096^2 use the smaller strip (two work-groups per CU, fewer walks per strip).
+#ifndef WSIMG_STRIP_CELLS
+#define WSIMG_STRIP_CELLS 8192
+#endif
+#ifndef WSIMG_STRIP_CELLS_SMALL
+#define WSIMG_STRIP_CELLS_SMALL 4096
+#endif
+// grid rows per strip below 4096^2 when > 0 (instead of STRIP_CELLS_SMALL / N, at most 4).
+// Two, the walk's register rows for W <= 7, so that a record visit decodes its record once:
+// 64 channels of 1024^2 10.0 -> 9.45 ms, 256^2 0.51 -> 0.36 ms, 2048^2 unchanged
+#ifndef WSIMG_STRIP_ROWS_SMALL
+#define WSIMG_STRIP_ROWS_SMALL 2
+#endif
+static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
+              "origins of a strip index an 8192-bin histogram");
+#ifndef WSIMG_F32_PX2
+#define WSIMG_F32_PX2 8192
+#endif
+#ifndef WSIMG_F64_PX2
+#define WSIMG_F64_PX2 4096
+#endif
+// Per image size: at 8192^2 a strip is one grid row, and with one column per layout block each
+// row element went to its own 64 KB-strided address (8-byte stores: 32 GB written for 9.3 GB of
+// strips on the LOFAR-shaped image).  Eight float columns per block make every row store a
+// whole 64-byte segment (gridding 28.9 -> 20.8 ms, stacking 12.1 -> 13.9 ms as each stacking
+// block now reads 8 of every 64 bytes: 47.7 -> 41.4 ms per image; 2, 4 and 16 columns: 45.9,
+// 43.3, 43.4 ms).  In double, 1, 2, 4 and 8 columns time alike (101-104 ms): one is kept.
+#ifndef WSIMG_F32_PX2_N13
+#define WSIMG_F32_PX2_N13 65536
+#endif
+#ifndef WSIMG_F64_PX2_N13
+#define WSIMG_F64_PX2_N13 8192
+#endif
+#ifndef WSIMG_F32_PX2_N12
+#define WSIMG_F32_PX2_N12 WSIMG_F32_PX2
+#endif
+#ifndef WSIMG_F64_PX2_N12
+#define WSIMG_F64_PX2_N12 WSIMG_F64_PX2
+#endif
+template <typename R, int LOG2N> constexpr int layout_pixels() {
+    if constexpr (sizeof(R) == 4) return LOG2N == 13 ? WSIMG_F32_PX2_N13 : (LOG2N == 12 ? WSIMG_F32_PX2_N12 : WSIMG_F32_PX2);
+    else return LOG2N == 13 ? WSIMG_F64_PX2_N13 : (LOG2N == 12 ? WSIMG_F64_PX2_N12 : WSIMG_F64_PX2);
+}
+// image columns per stacking block (0: all B columns of a layout block).  float: one, so that
+// several blocks share a CU and one block's barriers overlap another's work (a 4096^2 image
+// of 32 planes: 1.44 -> 1.26 ms with radix-8 passes, 1.18 ms with radix 16: 256 threads per
+// block, two blocks per CU)
+#ifndef WSIMG_F32_BS
+#define WSIMG_F32_BS 1
+#endif
+#ifndef WSIMG_F64_BS
+#define WSIMG_F64_BS 0
+#endif
+// 1: stacking blocks that share layout blocks are placed on one XCD (below)
+#ifndef WSIMG_COLS_XCD_MAP
+#define WSIMG_COLS_XCD_MAP 1
+#endif
+// column blocks per XCD group (0: one 128-byte line of image pixels per row)
+#ifndef WSIMG_COLS_XCD_Q
+#define WSIMG_COLS_XCD_Q 0
+#endif
 
-    // bytes of the stacking pass's LDS plane-flag table: the largest plane count a plan takes
-    constexpr size_t kPlaneTab = 4096;
+// bytes of the stacking pass's LDS plane-flag table: the largest plane count a plan takes
+constexpr size_t kPlaneTab = 4096;
 
-    template <typename R, int LOG2N> struct Shape {
-        static constexpr int N = 1 << LOG2N;
-        // base radices (log2), at most log2(N) - 1 so that a transform has two passes or more
-        static constexpr int LR1_0 = sizeof(R) == 4 ? WSIMG_F32_LR1 : WSIMG_F64_LR1;
-        static constexpr int LR2_0 = sizeof(R) == 4 ? f32_stack_radix_log2<LOG2N>() : WSIMG_F64_LR2;
-        static constexpr int LR1 = LR1_0 < LOG2N ? LR1_0 : LOG2N - 1;
-        static constexpr int LR2 = LR2_0 < LOG2N ? LR2_0 : LOG2N - 1;
-        static constexpr int E1 = 1 << LR1, E2 = 1 << LR2;
-        static constexpr int LR2A_0 = sizeof(R) == 4 ? WSIMG_F32_LR2A : WSIMG_F64_LR2A;
-        static constexpr int LR2A = LR2A_0 < LOG2N ? LR2A_0 : LOG2N - 1;
-        static constexpr int CAP1 = LOG2N >= 12 ? WSIMG_STRIP_CELLS : WSIMG_STRIP_CELLS_SMALL;
-        // a row at least; at most 4, so that small images still have many strips in flight and
-        // few register walks per strip (a 256^2 image: 1.18 ms with 16-row strips)
-        static constexpr int H0 = (LOG2N < 12 && WSIMG_STRIP_ROWS_SMALL > 0) ? WSIMG_STRIP_ROWS_SMALL
-                                  : (CAP1 / N < 4 ? (CAP1 / N < 1 ? 1 : CAP1 / N) : 4);
-        static constexpr int H = H0 < N / 2 ? H0 : N / 2;
-        static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);
-        static constexpr int PX2 = layout_pixels<R, LOG2N>();
-        // the intermediate holds B columns side by side per row (the gridding pass's write unit); a
-        // stacking block takes BS <= B of them and a prediction column block BA <= B
-        static constexpr int B0 = PX2 / N < N / 2 ? PX2 / N : N / 2;   // at most half a (padded) grid
-        static constexpr int B = B0 < 1 ? 1 : B0;
-        // the column blocks the work-groups of the column passes can hold in LDS
-        static constexpr int PXA = sizeof(R) == 4 ? WSIMG_F32_PX2 : WSIMG_F64_PX2;
-        static constexpr int BA0 = PXA / N < 1 ? 1 : PXA / N;
-        static constexpr int BA = BA0 < B ? BA0 : B;
-        static constexpr int BS0 = sizeof(R) == 4 ? WSIMG_F32_BS : WSIMG_F64_BS;
-        static constexpr int BS = BS0 <= 0 ? BA : (BS0 > B ? B : BS0);
-        static_assert((BS & (BS - 1)) == 0 && (BA & (BA - 1)) == 0, "column blocks: powers of two");
-        static constexpr int NT2 = (BS * N / E2) < 64 ? 64 : (BS * N / E2);   // stacking
-        static constexpr int NT2A = (BA * N >> LR2A) < 64 ? 64 : (BA * N >> LR2A);   // prediction column pass
-        static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
-        static constexpr size_t LDS1_BYTES = (size_t)LDS1 * sizeof(double2);   // float64 accumulation
-        static constexpr int LDS2 = lds_padded_elems_c(BA * N);                // complex elements
-        static constexpr size_t LDS2_BYTES = (size_t)LDS2 * 2 * sizeof(R);      // column pass of prediction
-        static constexpr int LDS2S = lds_padded_elems_c(BS * N);               // stacking FFT buffer
-        static constexpr size_t LDS2S_BUF = (size_t)LDS2S * 2 * sizeof(R);
-        // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer and the plane
-        // flags (kPlaneTab bytes, after everything else), else it stays in registers
-        static constexpr bool NM1_LDS = LDS2S_BUF + sizeof(double) * E2 * NT2 + kPlaneTab <= 160 * 1024;
-        static constexpr size_t PTAB_OFF = LDS2S_BUF + (NM1_LDS ? sizeof(double) * E2 * NT2 : 0);
-        static constexpr size_t LDS2S_BYTES = PTAB_OFF + kPlaneTab;
-    };
+template <typename R, int LOG2N> struct Shape {
+    static constexpr int N = 1 << LOG2N;
+    // base radices (log2), at most log2(N) - 1 so that a transform has two passes or more
+    static constexpr int LR1_0 = sizeof(R) == 4 ? (LOG2N == 13 ? WSIMG_F32_LR1_N13 : WSIMG_F32_LR1) : WSIMG_F64_LR1;
+    static constexpr int LR2_0 = sizeof(R) == 4 ? f32_stack_radix_log2<LOG2N>() : WSIMG_F64_LR2;
+    static constexpr int LR1 = LR1_0 < LOG2N ? LR1_0 : LOG2N - 1;
+    static constexpr int LR2 = LR2_0 < LOG2N ? LR2_0 : LOG2N - 1;
+    static constexpr int E1 = 1 << LR1, E2 = 1 << LR2;
+    static constexpr int LR2A_0 = sizeof(R) == 4 ? WSIMG_F32_LR2A : WSIMG_F64_LR2A;
+    static constexpr int LR2A = LR2A_0 < LOG2N ? LR2A_0 : LOG2N - 1;
+    static constexpr int CAP1 = LOG2N >= 12 ? WSIMG_STRIP_CELLS : WSIMG_STRIP_CELLS_SMALL;
+    // a row at least; at most 4, so that small images still have many strips in flight and
+    // few register walks per strip (a 256^2 image: 1.18 ms with 16-row strips)
+    static constexpr int H0 = (LOG2N < 12 && WSIMG_STRIP_ROWS_SMALL > 0) ? WSIMG_STRIP_ROWS_SMALL
+                              : (CAP1 / N < 4 ? (CAP1 / N < 1 ? 1 : CAP1 / N) : 4);
+    static constexpr int H = H0 < N / 2 ? H0 : N / 2;
+    static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);
+    static constexpr int PX2 = layout_pixels<R, LOG2N>();
+    // the intermediate holds B columns side by side per row (the gridding pass's write unit); a
+    // stacking block takes BS <= B of them and a prediction column block BA <= B
+    static constexpr int B0 = PX2 / N < N / 2 ? PX2 / N : N / 2;   // at most half a (padded) grid
+    static constexpr int B = B0 < 1 ? 1 : B0;
+    // the column blocks the work-groups of the column passes can hold in LDS
+    static constexpr int PXA = sizeof(R) == 4 ? WSIMG_F32_PX2 : WSIMG_F64_PX2;
+    static constexpr int BA0 = PXA / N < 1 ? 1 : PXA / N;
+    static constexpr int BA = BA0 < B ? BA0 : B;
+    static constexpr int BS0 = sizeof(R) == 4 ? WSIMG_F32_BS : WSIMG_F64_BS;
+    static constexpr int BS = BS0 <= 0 ? BA : (BS0 > B ? B : BS0);
+    static_assert((BS & (BS - 1)) == 0 && (BA & (BA - 1)) == 0, "column blocks: powers of two");
+    static constexpr int NT2 = (BS * N / E2) < 64 ? 64 : (BS * N / E2);   // stacking
+    static constexpr int NT2A = (BA * N >> LR2A) < 64 ? 64 : (BA * N >> LR2A);   // prediction column pass
+    static constexpr int LDS1 = lds_padded_elems_c(H * N);                 // elements
+    static constexpr size_t LDS1_BYTES = (size_t)LDS1 * sizeof(double2);   // float64 accumulation
+    static constexpr int LDS2 = lds_padded_elems_c(BA * N);                // complex elements
+    static constexpr size_t LDS2_BYTES = (size_t)LDS2 * 2 * sizeof(R);      // column pass of prediction
+    static constexpr int LDS2S = lds_padded_elems_c(BS * N);               // stacking FFT buffer
+    static constexpr size_t LDS2S_BUF = (size_t)LDS2S * 2 * sizeof(R);
+    // the per-pixel n - 1 table goes to LDS when it fits beside the FFT buffer and the plane
+    // flags (kPlaneTab bytes, after everything else), else it stays in registers
+    static constexpr bool NM1_LDS = LDS2S_BUF + sizeof(double) * E2 * NT2 + kPlaneTab <= 160 * 1024;
+    static constexpr size_t PTAB_OFF = LDS2S_BUF + (NM1_LDS ? sizeof(double) * E2 * NT2 : 0);
+    static constexpr size_t LDS2S_BYTES = PTAB_OFF + kPlaneTab;
+};
 
-    // ---------------------------------------------------------------------------------------
-    // gridding (+ row FFT) of one (plane, strip) in LDS
+// ---------------------------------------------------------------------------------------
+// gridding (+ row FFT) of one (plane, strip) in LDS
 
-    // The strip's cells accumulate in float64 in LDS for both precisions: with no grid padding
-    // the taper division amplifies grid rounding near the image edge by up to 1/C(1/2)^2 (about
-    // 2500 for W = 7), and float32 atomic accumulation alone costs ~1e-5 of the image there.
-    // The per-tap products are formed in the plan's precision; the float path converts the
-    // strip to float32 in place before its FFT.
-    //
-    // Each lane walks a chunk of consecutive records (records are in (bucket, origin) order) for
-    // RW grid rows of the strip at a time, summing the taps of a run of equal-origin records in
-    // float64 registers (RW x WMAX complex values; each tap product is still formed in the plan
-    // precision, so the sums match per-tap float64 accumulation up to order) and adding them to
-    // the LDS strip when the origin changes or the chunk ends.  (Float32 run sums cost up to
-    // 4e-6 of the image peak near the edges, where the taper amplifies grid rounding.)  The chunk length grows with the records the
-    // strip reads (one record per lane up to NT records, at most kChunkMax), so sparse strips
-    // keep every lane busy and dense ones merge long runs.
-    #ifndef WSIMG_GRID_BATCH
-    #define WSIMG_GRID_BATCH 4
-    #endif
-    #ifndef WSIMG_GRID_CHUNK_MAX
-    #define WSIMG_GRID_CHUNK_MAX 16
-    #endif
-    constexpr uint32_t kChunkMax = WSIMG_GRID_CHUNK_MAX;
+// The strip's cells accumulate in float64 in LDS for both precisions: with no grid padding
+// the taper division amplifies grid rounding near the image edge by up to 1/C(1/2)^2 (about
+// 2500 for W = 7), and float32 atomic accumulation alone costs ~1e-5 of the image there.
+// The per-tap products are formed in the plan's precision; the float path converts the
+// strip to float32 in place before its FFT.
+//
+// Each lane walks a chunk of consecutive records (records are in (bucket, origin) order) for
+// RW grid rows of the strip at a time, summing the taps of a run of equal-origin records in
+// float64 registers (RW x WMAX complex values; each tap product is still formed in the plan
+// precision, so the sums match per-tap float64 accumulation up to order) and adding them to
+// the LDS strip when the origin changes or the chunk ends.  (Float32 run sums cost up to
+// 4e-6 of the image peak near the edges, where the taper amplifies grid rounding.)  The chunk length grows with the records the
+// strip reads (one record per lane up to NT records, at most kChunkMax), so sparse strips
+// keep every lane busy and dense ones merge long runs.
+#ifndef WSIMG_GRID_BATCH
+#define WSIMG_GRID_BATCH 4
+#endif
+#ifndef WSIMG_GRID_CHUNK_MAX
+#define WSIMG_GRID_CHUNK_MAX 16
+#endif
+constexpr uint32_t kChunkMax = WSIMG_GRID_CHUNK_MAX;
 
-    // Register rows per walk for a support class WMAX: the float64 run sums (4 VGPRs per tap)
-    // stay within WSIMG_WALK_VGPRS registers.
-    #ifndef WSIMG_WALK_VGPRS
-    #define WSIMG_WALK_VGPRS 64
-    #endif
-    template <typename R, int WMAX> struct WalkRows {
-        static constexpr int words = WMAX * 4;
-        static constexpr int fit = WSIMG_WALK_VGPRS / words;
-        static constexpr int value = fit >= 8 ? 8 : (fit >= 4 ? 4 : (fit >= 2 ? 2 : 1));
-    };
+// Register rows per walk for a support class WMAX: the float64 run sums (4 VGPRs per tap)
+// stay within WSIMG_WALK_VGPRS registers.
+#ifndef WSIMG_WALK_VGPRS
+#define WSIMG_WALK_VGPRS 64
+#endif
+template <typename R, int WMAX> struct WalkRows {
+    static constexpr int words = WMAX * 4;
+    static constexpr int fit = WSIMG_WALK_VGPRS / words;
+    static constexpr int value = fit >= 8 ? 8 : (fit >= 4 ? 4 : (fit >= 2 ? 2 : 1));
+};
 
-    // One occupied strip (plane k of channel c, strip s) by the whole work-group.
-    // aux: the list entry's companion word (parts = 1 when not split); split_acc / split_done:
-    // the slots of split strips (float64 strip sums, completed-part counters).
-    template <typename R, bool FFT, int LOG2N, int WMAX>
-    __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, unsigned char* smem_raw,
-                                               const uint32_t* __restrict__ offsets,
-                                               const uint32_t* __restrict__ rec_cell,
-                                               const void* __restrict__ rec,
-                                               const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
-                                               typename Cx<R>::T* __restrict__ out, const R* __restrict__ kbw,
-                                               const R* __restrict__ recw, uint32_t aux = 1u,
-                                               double2* __restrict__ split_acc = nullptr,
-                                               uint32_t* __restrict__ split_done = nullptr) {
-        using C = typename Cx<R>::T;
-        using SH = Shape<R, LOG2N>;
-        constexpr int n = SH::N, H = SH::H, NT = SH::NT1, nmask = n - 1;
-        constexpr int LOG2H = Log2Of<H>::value_any;
-        constexpr int elems = H * n;
-        constexpr int RW = WalkRows<R, WMAX>::value < H ? WalkRows<R, WMAX>::value : H;
-        constexpr int NG = H / RW, LOG2NG = Log2Of<NG>::value_any;
-        double2* acc = reinterpret_cast<double2*>(smem_raw);
-        C* lds = reinterpret_cast<C*>(smem_raw);
-        const int tid = threadIdx.x;
-        const int row0 = s * H;
-        for (int e = tid; e < SH::LDS1; e += NT) acc[e] = make_double2(0.0, 0.0);
-        __syncthreads();
+// One occupied strip (plane k of channel c, strip s) by the whole work-group.
+// aux: the list entry's companion word (parts = 1 when not split); split_acc / split_done:
+// the slots of split strips (float64 strip sums, completed-part counters).
+template <typename R, bool FFT, int LOG2N, int WMAX>
+__device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, unsigned char* smem_raw,
+                                           const uint32_t* __restrict__ offsets,
+                                           const uint32_t* __restrict__ rec_cell,
+                                           const void* __restrict__ rec,
+                                           const R* __restrict__ kbc, const typename Cx<R>::T* __restrict__ tw,
+                                           typename Cx<R>::T* __restrict__ out, const R* __restrict__ kbw,
+                                           const R* __restrict__ recw, uint32_t aux = 1u,
+                                           double2* __restrict__ split_acc = nullptr,
+                                           uint32_t* __restrict__ split_done = nullptr) {
+    using C = typename Cx<R>::T;
+    using SH = Shape<R, LOG2N>;
+    constexpr int n = SH::N, H = SH::H, NT = SH::NT1, nmask = n - 1;
+    constexpr int LOG2H = Log2Of<H>::value_any;
+    constexpr int elems = H * n;
+    constexpr int RW = WalkRows<R, WMAX>::value < H ? WalkRows<R, WMAX>::value : H;
+    constexpr int NG = H / RW, LOG2NG = Log2Of<NG>::value_any;
+    double2* acc = reinterpret_cast<double2*>(smem_raw);
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int row0 = s * H;
+    for (int e = tid; e < SH::LDS1; e += NT) acc[e] = make_double2(0.0, 0.0);
+    __syncthreads();
 
-        const int W = g.support, hW = g.half;
-        constexpr int TC = WMAX / 2;               // centre slot of the tap arrays
-        int s_lo = (row0 - (W - 1)) >> LOG2H;
-        if (s_lo < 0) s_lo = 0;
-        constexpr int shift = FFT ? (n >> 1) : 0;   // place cell q at (q + n/2) mod n: the centring
-        const uint32_t parts = aux & 0xFFu, part = (aux >> 8) & 0xFFu, slot = aux >> 16;
-        // the rows of plane kk reach plane k: kk = k, or kk = k - Ww + 1 .. k with the w-kernel,
-        // whose rows then carry the weight of their w-tap wj = k - kk (split strips: one plane)
-        const int klo = g.wsup ? (k - g.wsup + 1 < 0 ? 0 : k - g.wsup + 1) : k;
-        for (int kk = klo; kk <= k; ++kk) {
+    const int W = g.support, hW = g.half;
+    constexpr int TC = WMAX / 2;               // centre slot of the tap arrays
+    int s_lo = (row0 - (W - 1)) >> LOG2H;
+    if (s_lo < 0) s_lo = 0;
+    constexpr int shift = FFT ? (n >> 1) : 0;   // place cell q at (q + n/2) mod n: the centring
+    const uint32_t parts = aux & 0xFFu, part = (aux >> 8) & 0xFFu, slot = aux >> 16;
+    // the rows of plane kk reach plane k: kk = k, or kk = k - Ww + 1 .. k with the w-kernel,
+    // whose rows then carry the weight of their w-tap wj = k - kk (split strips: one plane)
+    const int klo = g.wsup ? (k - g.wsup + 1 < 0 ? 0 : k - g.wsup + 1) : k;
+    for (int kk = klo; kk <= k; ++kk) {
         const int wj = k - kk;
         const int bucket0 = c * g.nb1 + kk * g.S;
         uint32_t vbeg = offsets[(size_t)(bucket0 + s_lo) << kLogReplicas];
@@ -1110,6 +1115,44 @@ k_occupancy(int nch, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __re
     }
 }
 
+// Next entry of the strip work list for a persistent work-group (one thread asks; -1: none
+// left).  Heavy entries (and split parts) go to whichever work-group asks first.  The light
+// entries lie in bucket order within the chunks of consecutive strips k_occupancy writes; they
+// are cut into 8 contiguous ranges, one per XCD (work-groups go to the XCDs round-robin, so
+// work-group x runs on XCD x mod 8), and the work-groups of an XCD take its range in order: the
+// strips an XCD grids at the same time are neighbours, whose records (a record's taps reach
+// (W + H - 2) / H + 1 strips) its L2 then serves to all of them.  An XCD whose range is done
+// takes entries from the others' ranges.
+#ifndef WSIMG_XCD_RANGES
+#define WSIMG_XCD_RANGES 1
+#endif
+__device__ __forceinline__ int fetch_item(WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
+                                          const uint32_t* __restrict__ list_aux, uint32_t list_cap,
+                                          uint32_t& aux) {
+    const unsigned n_heavy = wl->n_heavy, n_light = wl->n_light;
+    aux = 1u;
+    if (!WSIMG_XCD_RANGES) {
+        const unsigned i = atomicAdd(&wl->next, 1u);
+        if (i < n_heavy) { aux = list_aux[i]; return (int)list[i]; }
+        if (i - n_heavy < n_light) return (int)list[list_cap - 1 - (i - n_heavy)];
+        return -1;
+    }
+    if (__hip_atomic_load(&wl->next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n_heavy) {
+        const unsigned i = atomicAdd(&wl->next, 1u);
+        if (i < n_heavy) { aux = list_aux[i]; return (int)list[i]; }
+    }
+    const int x0 = (int)(blockIdx.x & 7u);
+    for (int t = 0; t < 8; ++t) {
+        const int x = (x0 + t) & 7;
+        const unsigned lo = (unsigned)(((uint64_t)n_light * (unsigned)x) >> 3);
+        const unsigned hi = (unsigned)(((uint64_t)n_light * (unsigned)(x + 1)) >> 3);
+        if (__hip_atomic_load(&wl->xnext[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo) continue;
+        const unsigned j = atomicAdd(&wl->xnext[x], 1u);
+        if (j < hi - lo) return (int)list[list_cap - 1 - (lo + j)];
+    }
+    return -1;
+}
+
 // The gridding step alone: work-group (b, c) = strip b of every plane of channel c; empty
 // strips are zeroed.
 template <typename R, int LOG2N, int WMAX>
@@ -1144,15 +1187,10 @@ k_grid_rows(Geom g, WorkList* __restrict__ wl, const uint32_t* __restrict__ list
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item;
     __shared__ uint32_t item_aux;
-    const unsigned n_heavy = wl->n_heavy, n_light = wl->n_light;
     while (true) {
         if (threadIdx.x == 0) {
-            const unsigned i = atomicAdd(&wl->next, 1u);
-            int b = -1;
             uint32_t x = 1u;
-            if (i < n_heavy) { b = (int)list[i]; x = list_aux[i]; }
-            else if (i - n_heavy < n_light) b = (int)list[list_cap - 1 - (i - n_heavy)];
-            item = b;
+            item = fetch_item(wl, list, list_aux, list_cap, x);
             item_aux = x;
         }
         __syncthreads();
@@ -1654,15 +1692,10 @@ k_adj_rows(Geom g, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item;
     __shared__ uint32_t item_aux;
-    const unsigned n_heavy = wl->n_heavy, n_light = wl->n_light;
     while (true) {
         if (threadIdx.x == 0) {
-            const unsigned i = atomicAdd(&wl->next, 1u);
-            int b = -1;
             uint32_t x = 1u;
-            if (i < n_heavy) { b = (int)list[i]; x = list_aux[i]; }
-            else if (i - n_heavy < n_light) b = (int)list[list_cap - 1 - (i - n_heavy)];
-            item = b;
+            item = fetch_item(wl, list, list_aux, list_cap, x);
             item_aux = x;
         }
         __syncthreads();

@@ -266,17 +266,21 @@ wsimg_status set_lds_limits(wsimg_plan* pl) {
 // only: in float64 the sort (36-byte records) costs more than the longer runs save (C2 float64
 // 5.79 -> 5.44 ms without it; float32 3.03 -> 3.00 ms with it), and its gridding reads the
 // records in bucket order.
-template <typename R> constexpr bool origin_sorted() { return sizeof(R) == 4; }
-constexpr bool origin_sorted_plan(bool f32) { return f32; }
+#ifndef WSIMG_ORIGIN_SORT_N13
+#define WSIMG_ORIGIN_SORT_N13 1
+#endif
+template <typename R> bool origin_sorted(int log2n) { return sizeof(R) == 4 && (log2n != 13 || WSIMG_ORIGIN_SORT_N13); }
+bool origin_sorted_plan(bool f32, int log2n) { return f32 && (log2n != 13 || WSIMG_ORIGIN_SORT_N13); }
 
 // WMAX: the support class the gridding registers are sized for (W <= 7, else W <= 15).
 template <typename R, int LOG2N, int WMAX>
 wsimg_status launch_grid_w(wsimg_plan* pl, int nch, bool fft, void* out) {
     using C = typename Cx<R>::T;
     const Geom g = pl->g;
-    const uint32_t* rc = origin_sorted<R>() ? pl->rec_cell2 : pl->rec_cell;
-    const void* rr = origin_sorted<R>() ? pl->rec2 : pl->rec;
-    const R* recw = g.wsup ? (const R*)(origin_sorted<R>() ? pl->rec_w2 : pl->rec_w) : nullptr;
+    const bool sorted = origin_sorted<R>(LOG2N);
+    const uint32_t* rc = sorted ? pl->rec_cell2 : pl->rec_cell;
+    const void* rr = sorted ? pl->rec2 : pl->rec;
+    const R* recw = g.wsup ? (const R*)(sorted ? pl->rec_w2 : pl->rec_w) : nullptr;
     if (fft) {
         hipLaunchKernelGGL((k_grid_rows<R, LOG2N, WMAX>), dim3((unsigned)pl->persist_blocks), dim3(pl->nt1),
                            pl->lds1, pl->stream, g, pl->worklist, pl->list, pl->list_aux, pl->list_cap,
@@ -536,7 +540,7 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     }
     if (auto r = st.after(4)) return r;
 
-    if (M > 0 && !predict && origin_sorted<R>()) {
+    if (M > 0 && !predict && origin_sorted<R>(g.log2n)) {
         hipLaunchKernelGGL((k_origin_sort<R>), dim3((unsigned)pl->nb, nch), dim3(kSortThreads), 0, s, g,
                            pl->offsets, pl->rec_cell, (const void*)pl->rec, pl->rec_cell2, pl->rec2,
                            g.wsup ? (const R*)pl->rec_w : nullptr, g.wsup ? (R*)pl->rec_w2 : nullptr);
@@ -695,7 +699,7 @@ wsimg_status for_each_allocation(wsimg_plan* pl, F&& f) {
     const size_t nbt = (size_t)pl->nb * mc;
     size_t nparts_alloc = 0;
     for (int c = 1; c <= pl->max_channels; ++c) nparts_alloc = std::max(nparts_alloc, (size_t)c * parts_target(c));
-    const bool sorted2 = origin_sorted_plan(f32);     // origin-ordered copies exist
+    const bool sorted2 = origin_sorted_plan(f32, g.log2n);     // origin-ordered copies exist
     const size_t rec_bytes = f32 ? 16 : 32;
     wsimg_status r = WSIMG_OK;
 #define WS_ALLOC(field, bytes, name) \
