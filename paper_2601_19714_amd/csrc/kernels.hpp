@@ -941,7 +941,10 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
             vend = pe;
         }
         const uint32_t nv = vend - vbeg;
-        uint32_t chunk = nv / NT;
+        // records per walk item: the fewest for which the strip's items (chunks x row groups)
+        // fit in one pass of the work-group (rounding down left e.g. 4260 records of a 512-thread
+        // group in 533 chunks of 8: two rounds, the second for 21 threads)
+        uint32_t chunk = (uint32_t)(((uint64_t)nv * NG + NT - 1) / NT);
         chunk = chunk < 1u ? 1u : (chunk > kChunkMax ? kChunkMax : chunk);
         const uint32_t items = ((nv + chunk - 1) / chunk) << LOG2NG;
 

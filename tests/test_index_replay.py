@@ -230,7 +230,7 @@ def replay(uvw, wt, freq, prm, info, prec):
             nv = pe - pb
             if nv <= 0:
                 continue
-            chunk = min(max(nv // NT, 1), CHUNK_MAX)
+            chunk = min(max(-(-(nv * NG) // NT), 1), CHUNK_MAX)
             items = -(-nv // chunk)
             last_r = pb + (items - 1) * chunk
             re = min(last_r + chunk, pe)
