@@ -1466,7 +1466,8 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
         if (last_slot<LOG2N, LR, BS, NT>(tid, s, col, ip)) {
             const int i = ((ip + hn) & nmask) - crop, j = (jb << LOG2BS) + col;
             if (!PAD || (i >= 0 && i < nimg)) {
-                const size_t o = (size_t)c * nimg * nimg + (size_t)i * nimg + j;
+                // column j of the transposed image (k_transpose makes it row-major)
+                const size_t o = (size_t)c * nimg * nimg + (size_t)j * nimg + i;
                 const R ti = inv_taper[i], tj = inv_taper[j];
                 // the w-kernel's transform at dw (n - 1) divides the image too
                 const R iw = g.wsup ? (R)(1.0 / kb_transform(dw * (SH::NM1_LDS ? nm1s[s * NT + tid]
@@ -1482,6 +1483,28 @@ k_cols_stack(Geom g, const Scalars* __restrict__ sc, const uint16_t* __restrict_
                 }
             }
         }
+    }
+}
+
+// The stacking pass writes the image transposed, [channel][column j][row i]: a stacking block
+// holds one (or a few) image columns, and written row-major its stores were 4-byte pieces of
+// lines shared with 31 other blocks, which reached HBM about 8x amplified (525 MB written for
+// the 67 MB of a 4096^2 image).  Column-major they are whole contiguous runs; this kernel then
+// moves 64 x 64 tiles through LDS into the row-major image.  Grid (ceil(n/64), ceil(n/64), nch).
+template <typename T>
+__global__ void __launch_bounds__(256) k_transpose(int n, const T* __restrict__ src, T* __restrict__ dst) {
+    __shared__ T tile[64][65];
+    const size_t plane = (size_t)n * n * blockIdx.z;
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;      // image rows i, columns j
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int j = j0 + r, i = i0 + tx;
+        if (j < n && i < n) tile[r][tx] = src[plane + (size_t)j * n + i];
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int i = i0 + r, j = j0 + tx;
+        if (i < n && j < n) dst[plane + (size_t)i * n + j] = tile[tx][r];
     }
 }
 

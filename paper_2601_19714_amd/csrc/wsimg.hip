@@ -88,6 +88,7 @@ struct wsimg_plan {
     void *rec = nullptr, *rec2 = nullptr, *inter = nullptr;   // records by bucket; by (bucket, origin)
     void *tw = nullptr, *inv_taper = nullptr, *kbc = nullptr;
     void *kbw = nullptr, *rec_w = nullptr, *rec_w2 = nullptr;   // w-kernel: polynomials, row offsets
+    void* image_t = nullptr;       // the stacking pass's column-major images
     int64_t device_bytes = 0;
     std::vector<void*> allocations;
     // timing
@@ -316,7 +317,7 @@ wsimg_status launch_cols(wsimg_plan* pl, int nch, void* image) {
     auto launch = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(pl->nt2), pl->lds2s, pl->stream, g, pl->scalars, pl->sflags,
                            pl->plane_occ, (const C*)pl->inter, (const C*)pl->tw, (const R*)pl->inv_taper,
-                           (R*)image);
+                           (R*)pl->image_t);
     };
     const bool cplx = (pl->p.flags & WSIMG_COMPLEX_OUT) != 0;
     if (g.crop > 0) {
@@ -327,6 +328,15 @@ wsimg_status launch_cols(wsimg_plan* pl, int nch, void* image) {
         else launch(k_cols_stack<R, LOG2N, false, false>);
     }
     WS_LAUNCH_CHECK("cols_stack");
+    // the column-major image -> the caller's row-major image
+    const unsigned tiles = (unsigned)((g.n_img + 63) / 64);
+    if (cplx)
+        hipLaunchKernelGGL(k_transpose<C>, dim3(tiles, tiles, (unsigned)nch), dim3(256), 0, pl->stream, g.n_img,
+                           (const C*)pl->image_t, (C*)image);
+    else
+        hipLaunchKernelGGL(k_transpose<R>, dim3(tiles, tiles, (unsigned)nch), dim3(256), 0, pl->stream, g.n_img,
+                           (const R*)pl->image_t, (R*)image);
+    WS_LAUNCH_CHECK("transpose");
     return WSIMG_OK;
 }
 
@@ -727,6 +737,8 @@ wsimg_status for_each_allocation(wsimg_plan* pl, F&& f) {
     WS_ALLOC(rec_idx, sizeof(uint32_t) * rows, "record rows");
     WS_ALLOC(rec2, sorted2 ? rec_bytes * rows : 256, "records by origin");
     WS_ALLOC(inter, pl->cbytes * cells * mc, "row-transformed planes");
+    WS_ALLOC(image_t, ((pl->p.flags & WSIMG_COMPLEX_OUT) ? pl->cbytes : pl->rbytes) * (size_t)g.n_img * g.n_img * mc,
+             "column-major images");
     WS_ALLOC(tw, pl->cbytes * g.n, "twiddles");
     WS_ALLOC(inv_taper, pl->rbytes * g.n_img, "taper");
     WS_ALLOC(kbc, pl->rbytes * (size_t)pl->p.support * 17, "kernel polynomials");
