@@ -602,6 +602,23 @@ __device__ __forceinline__ void decode_record(const RawRec<R>& x, int strip, int
     }
 }
 
+// A lane's record (or value) from lane src of the wave.
+template <typename R> __device__ __forceinline__ R shfl_real(R v, int src) { return __shfl(v, src, 64); }
+template <typename R> __device__ __forceinline__ RawRec<R> shfl_record(const RawRec<R>& x, int src) {
+    RawRec<R> y;
+    if constexpr (sizeof(R) == 4) {
+        y.q.x = (uint32_t)__shfl((int)x.q.x, src, 64);
+        y.q.y = (uint32_t)__shfl((int)x.q.y, src, 64);
+        y.q.z = (uint32_t)__shfl((int)x.q.z, src, 64);
+        y.q.w = (uint32_t)__shfl((int)x.q.w, src, 64);
+    } else {
+        y.cell = (uint32_t)__shfl((int)x.cell, src, 64);
+        y.f.x = __shfl(x.f.x, src, 64); y.f.y = __shfl(x.f.y, src, 64);
+        y.v.x = __shfl(x.v.x, src, 64); y.v.y = __shfl(x.v.y, src, 64);
+    }
+    return y;
+}
+
 // Origin index q0 * H + (p0 mod H) of a stored record (< H * N <= 8192).
 template <typename R>
 __device__ __forceinline__ uint32_t raw_origin(const RawRec<R>& x, int log2H) {
@@ -637,6 +654,38 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
         if (end - beg == 1 && t == 0) {
             store_record<R>(rec_cell2, rec2, beg, fetch_record<R>(rec_cell, rec, beg));
             if (rec_w) rec_w2[beg] = rec_w[beg];
+        }
+        return;
+    }
+    if (end - beg <= 64) {
+        // a small bucket (half the non-empty ones on an 8192^2 grid): one wave sorts it with a
+        // bitonic network over the lanes, on (origin, position) so equal origins keep their
+        // order; no histogram, no barrier
+        if (t >= 64) return;
+        const uint32_t nb = end - beg;
+        RawRec<R> x{};
+        R xw = (R)0;
+        uint32_t key = 0xFFFFFFFFu;
+        if ((uint32_t)t < nb) {
+            x = fetch_record<R>(rec_cell, rec, beg + t);
+            if (rec_w) xw = rec_w[beg + t];
+            key = (raw_origin<R>(x, g.log2H) << 6) | (uint32_t)t;
+        }
+#pragma unroll
+        for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                const uint32_t o = (uint32_t)__shfl_xor((int)key, stride, 64);
+                const bool asc = (t & size) == 0 || size == 64, low = (t & stride) == 0;
+                key = (low == asc) ? (key < o ? key : o) : (key > o ? key : o);
+            }
+        }
+        const int src = (int)(key & 63u);
+        RawRec<R> y = shfl_record<R>(x, src);
+        const R yw = rec_w ? shfl_real<R>(xw, src) : (R)0;
+        if ((uint32_t)t < nb) {
+            store_record<R>(rec_cell2, rec2, beg + t, y);
+            if (rec_w) rec_w2[beg + t] = yw;
         }
         return;
     }
