@@ -810,6 +810,24 @@ template <int LOG2N> constexpr int f32_stack_radix_log2() {
 #ifndef WSIMG_STRIP_ROWS_SMALL
 #define WSIMG_STRIP_ROWS_SMALL 2
 #endif
+// per image size (log2 n < 12) override of the rows per strip (0: by cells, at most 4).  At
+// 1024^2 four rows beat two once the walk's chunks were rounded up (64 channels: 11.4 against
+// 13.7 ms), while 256^2 keeps two (0.39 against 0.54 ms).
+#ifndef WSIMG_STRIP_ROWS_N10
+#define WSIMG_STRIP_ROWS_N10 0
+#endif
+template <int LOG2N> constexpr int strip_rows_small() {
+#ifdef WSIMG_STRIP_ROWS_N8
+    if (LOG2N == 8) return WSIMG_STRIP_ROWS_N8;
+#endif
+#ifdef WSIMG_STRIP_ROWS_N9
+    if (LOG2N == 9) return WSIMG_STRIP_ROWS_N9;
+#endif
+#ifdef WSIMG_STRIP_ROWS_N11
+    if (LOG2N == 11) return WSIMG_STRIP_ROWS_N11;
+#endif
+    return LOG2N == 10 ? WSIMG_STRIP_ROWS_N10 : WSIMG_STRIP_ROWS_SMALL;
+}
 static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
               "origins of a strip index an 8192-bin histogram");
 #ifndef WSIMG_F32_PX2
@@ -875,7 +893,8 @@ template <typename R, int LOG2N> struct Shape {
     static constexpr int CAP1 = LOG2N >= 12 ? WSIMG_STRIP_CELLS : WSIMG_STRIP_CELLS_SMALL;
     // a row at least; at most 4, so that small images still have many strips in flight and
     // few register walks per strip (a 256^2 image: 1.18 ms with 16-row strips)
-    static constexpr int H0 = (LOG2N < 12 && WSIMG_STRIP_ROWS_SMALL > 0) ? WSIMG_STRIP_ROWS_SMALL
+    static constexpr int HS = strip_rows_small<LOG2N>();
+    static constexpr int H0 = (LOG2N < 12 && HS > 0) ? HS
                               : (CAP1 / N < 4 ? (CAP1 / N < 1 ? 1 : CAP1 / N) : 4);
     static constexpr int H = H0 < N / 2 ? H0 : N / 2;
     static constexpr int NT1 = (H * N / E1) < 64 ? 64 : (H * N / E1);

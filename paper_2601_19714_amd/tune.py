@@ -38,12 +38,17 @@ CANDIDATES = {
     "defaults": [],
     "stack_r8": ["-DWSIMG_F32_LR2_N{L}=3"],
     "stack_r16": ["-DWSIMG_F32_LR2_N{L}=4"],
-    "stack_b2": ["-DWSIMG_F32_BS=0", "-DWSIMG_F32_LR2=3"],
-    "strip_rows_by_cells": ["-DWSIMG_STRIP_ROWS_SMALL=0"],
+    "strip_rows2": ["-DWSIMG_STRIP_ROWS_N{L}=2"],
+    "strip_rows4": ["-DWSIMG_STRIP_ROWS_N{L}=4"],
     "chunk32": ["-DWSIMG_GRID_CHUNK_MAX=32"],
-    "tw_table": ["-DWSIMG_TW_DERIVE=0"],
     "walk128": ["-DWSIMG_WALK_VGPRS=128"],
-    "xcd_pairs": ["-DWSIMG_COLS_XCD_Q=1"],
+}
+# the image sizes (log2 n) a per-shape candidate's macro applies to
+APPLIES = {
+    "stack_r8": lambda L: L >= 10,
+    "stack_r16": lambda L: L >= 10,
+    "strip_rows2": lambda L: L < 12,
+    "strip_rows4": lambda L: L < 12,
 }
 
 WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5}
@@ -64,7 +69,8 @@ def variants(workloads):
     for name, flags in CANDIDATES.items():
         if per_shape(name):
             for L in shapes:
-                out.append((f"{name}_n{L}", name, L, [f.replace("{L}", str(L)) for f in flags]))
+                if APPLIES.get(name, lambda _: True)(L):
+                    out.append((f"{name}_n{L}", name, L, [f.replace("{L}", str(L)) for f in flags]))
         else:
             out.append((name, name, None, list(flags)))
     return out
@@ -200,11 +206,11 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     b = sub.add_parser("build")
     b.add_argument("--out", default=DEFAULT_DIR)
-    b.add_argument("--workloads", default="c2,c3,c4")
+    b.add_argument("--workloads", default="c1,c2,c3,c4")
     b.add_argument("--only", default="", help="comma-separated candidate names (default: all)")
     t = sub.add_parser("time")
     t.add_argument("--dir", default=DEFAULT_DIR)
-    t.add_argument("--workloads", default="c2,c3,c4")
+    t.add_argument("--workloads", default="c1,c2,c3,c4")
     t.add_argument("--steps", type=int, default=10)
     t.add_argument("--warmup", type=int, default=2)
     t.add_argument("--timeout", type=int, default=240)

@@ -62,7 +62,8 @@ def shape(prec, log2n):
     lr1 = min(4, log2n - 1)
     lr2 = min((4 if log2n == 12 else 3) if f32 else 3, log2n - 1)
     cap1 = 8192 if log2n >= 12 else 4096
-    h0 = 2 if log2n < 12 else min(4, max(1, cap1 // N))
+    hs = 0 if log2n == 10 else 2                              # rows per strip below 4096^2 (0: by cells)
+    h0 = hs if (log2n < 12 and hs > 0) else min(4, max(1, cap1 // N))
     H = min(h0, N // 2)
     nt1 = max(64, H * N >> lr1)
     pxa = 8192 if f32 else 4096                              # column-pass work-group pixels
