@@ -65,9 +65,13 @@ struct Scalars {
 // The gridding work list of occupied strips of all channels: heavy ones from the front,
 // light ones from the back; next is the persistent kernel's fetch counter, n_split the number
 // of strips split into parts (below).
+// Each fetch counter has a 128-byte line of its own: the eight per-XCD counters on one line
+// made the atomics of the whole grid queue on it (64 channels of 1024^2: gridding 6.2 ms against
+// 4.4 ms with a line each; 8192^2: 16.9 against 16.4 ms).
 struct WorkList {
-    unsigned int n_heavy, n_light, next, n_split;
-    unsigned int xnext[8];      // per-XCD counters over the light entries (fetch_item)
+    unsigned int n_heavy, n_light, n_split, pad0[29];
+    unsigned int next, pad1[31];
+    struct { unsigned int n, pad[31]; } xnext[8];   // per-XCD counters over the light entries
 };
 
 // Heavy strips are split.  With `share` the record visits of the call over the gridding
@@ -247,7 +251,7 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
         r.n_occ = 0;
         r.n_planes = 0;
         sc[c] = r;
-        if (c == 0) *wl = WorkList{0u, 0u, 0u, 0u, {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u}};
+        if (c == 0) *wl = WorkList{};
     }
 }
 
@@ -807,12 +811,9 @@ template <int LOG2N> constexpr int f32_stack_radix_log2() {
 #ifndef WSIMG_STRIP_ROWS_SMALL
 #define WSIMG_STRIP_ROWS_SMALL 2
 #endif
-// per image size (log2 n < 12) override of the rows per strip (0: by cells, at most 4).  At
-// 1024^2 four rows beat two once the walk's chunks were rounded up (64 channels: 11.4 against
-// 13.7 ms), while 256^2 keeps two (0.39 against 0.54 ms).
-#ifndef WSIMG_STRIP_ROWS_N10
-#define WSIMG_STRIP_ROWS_N10 0
-#endif
+// WSIMG_STRIP_ROWS_N<log2 n> (n < 4096) sets one size (the autotuner's per-shape choices; 0:
+// by cells, at most 4).  64 channels of 1024^2 grid in 3.8 ms with two rows against 4.4 ms with
+// four.
 template <int LOG2N> constexpr int strip_rows_small() {
 #ifdef WSIMG_STRIP_ROWS_N8
     if (LOG2N == 8) return WSIMG_STRIP_ROWS_N8;
@@ -820,10 +821,13 @@ template <int LOG2N> constexpr int strip_rows_small() {
 #ifdef WSIMG_STRIP_ROWS_N9
     if (LOG2N == 9) return WSIMG_STRIP_ROWS_N9;
 #endif
+#ifdef WSIMG_STRIP_ROWS_N10
+    if (LOG2N == 10) return WSIMG_STRIP_ROWS_N10;
+#endif
 #ifdef WSIMG_STRIP_ROWS_N11
     if (LOG2N == 11) return WSIMG_STRIP_ROWS_N11;
 #endif
-    return LOG2N == 10 ? WSIMG_STRIP_ROWS_N10 : WSIMG_STRIP_ROWS_SMALL;
+    return WSIMG_STRIP_ROWS_SMALL;
 }
 static_assert(WSIMG_STRIP_CELLS <= 8192 && WSIMG_STRIP_CELLS_SMALL <= 8192,
               "origins of a strip index an 8192-bin histogram");
@@ -1187,26 +1191,35 @@ __device__ __forceinline__ void grid_strip(const Geom& g, int c, int k, int s, u
 // work-group x runs on XCD x mod 8), and the work-groups of an XCD take its range in order: the
 // strips an XCD grids at the same time are neighbours, whose records (a record's taps reach
 // (W + H - 2) / H + 1 strips) its L2 then serves to all of them.  An XCD whose range is done
-// takes entries from the others' ranges.
+// takes entries from the others' ranges.  The asking thread keeps a mask of the sources it has
+// found exhausted (bit 8: the heavy entries), so that a work-group that has moved on to other
+// ranges does not ask the spent counters again (each question is an agent-scope load past the
+// XCD's L2: 4% of the gridding of 64 channels of 1024^2, whose strips take tens of us each),
+// and the list's two lengths are read once per work-group.
 // (One global counter over the whole list, the earlier scheme, gridded the 8192^2 LOFAR-shaped
 // image in 19.3 ms against 17.7 ms, and 4096^2 in 1.13 against 1.09 ms.)
 __device__ __forceinline__ int fetch_item(WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
                                           const uint32_t* __restrict__ list_aux, uint32_t list_cap,
-                                          uint32_t& aux) {
-    const unsigned n_heavy = wl->n_heavy, n_light = wl->n_light;
+                                          unsigned n_heavy, unsigned n_light, uint32_t& aux, uint32_t& spent) {
     aux = 1u;
-    if (__hip_atomic_load(&wl->next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n_heavy) {
-        const unsigned i = atomicAdd(&wl->next, 1u);
-        if (i < n_heavy) { aux = list_aux[i]; return (int)list[i]; }
+    if (!(spent & 0x100u)) {
+        if (__hip_atomic_load(&wl->next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n_heavy) {
+            const unsigned i = atomicAdd(&wl->next, 1u);
+            if (i < n_heavy) { aux = list_aux[i]; return (int)list[i]; }
+        }
+        spent |= 0x100u;
     }
     const int x0 = (int)(blockIdx.x & 7u);
     for (int t = 0; t < 8; ++t) {
         const int x = (x0 + t) & 7;
+        if (spent & (1u << x)) continue;
         const unsigned lo = (unsigned)(((uint64_t)n_light * (unsigned)x) >> 3);
         const unsigned hi = (unsigned)(((uint64_t)n_light * (unsigned)(x + 1)) >> 3);
-        if (__hip_atomic_load(&wl->xnext[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo) continue;
-        const unsigned j = atomicAdd(&wl->xnext[x], 1u);
-        if (j < hi - lo) return (int)list[list_cap - 1 - (lo + j)];
+        if (__hip_atomic_load(&wl->xnext[x].n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hi - lo) {
+            const unsigned j = atomicAdd(&wl->xnext[x].n, 1u);
+            if (j < hi - lo) return (int)list[list_cap - 1 - (lo + j)];
+        }
+        spent |= 1u << x;
     }
     return -1;
 }
@@ -1245,10 +1258,13 @@ k_grid_rows(Geom g, WorkList* __restrict__ wl, const uint32_t* __restrict__ list
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item;
     __shared__ uint32_t item_aux;
+    uint32_t spent = 0u;        // thread 0's mask of exhausted work-list sources
+    unsigned n_heavy = 0u, n_light = 0u;
+    if (threadIdx.x == 0) { n_heavy = wl->n_heavy; n_light = wl->n_light; }
     while (true) {
         if (threadIdx.x == 0) {
             uint32_t x = 1u;
-            item = fetch_item(wl, list, list_aux, list_cap, x);
+            item = fetch_item(wl, list, list_aux, list_cap, n_heavy, n_light, x, spent);
             item_aux = x;
         }
         __syncthreads();
@@ -1773,10 +1789,13 @@ k_adj_rows(Geom g, WorkList* __restrict__ wl, const uint32_t* __restrict__ list,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int item;
     __shared__ uint32_t item_aux;
+    uint32_t spent = 0u;        // thread 0's mask of exhausted work-list sources
+    unsigned n_heavy = 0u, n_light = 0u;
+    if (threadIdx.x == 0) { n_heavy = wl->n_heavy; n_light = wl->n_light; }
     while (true) {
         if (threadIdx.x == 0) {
             uint32_t x = 1u;
-            item = fetch_item(wl, list, list_aux, list_cap, x);
+            item = fetch_item(wl, list, list_aux, list_cap, n_heavy, n_light, x, spent);
             item_aux = x;
         }
         __syncthreads();

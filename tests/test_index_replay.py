@@ -62,7 +62,7 @@ def shape(prec, log2n):
     lr1 = min(4, log2n - 1)
     lr2 = min((4 if log2n == 12 else 3) if f32 else 3, log2n - 1)
     cap1 = 8192 if log2n >= 12 else 4096
-    hs = 0 if log2n == 10 else 2                              # rows per strip below 4096^2 (0: by cells)
+    hs = 2                                                    # rows per strip below 4096^2 (0: by cells)
     h0 = hs if (log2n < 12 and hs > 0) else min(4, max(1, cap1 // N))
     H = min(h0, N // 2)
     nt1 = max(64, H * N >> lr1)
