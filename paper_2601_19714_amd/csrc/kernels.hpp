@@ -256,7 +256,7 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
 }
 
 // Bucket counters are replicated kReplicas times, laid out [bucket][replica]; the rows of
-// row block b of a channel (kKeyThreads rows) count in replica b mod kReplicas.  The rows of one hot
+// row block b of a channel (kKeyRows rows) count in replica b mod kReplicas.  The rows of one hot
 // bucket (tens of thousands near the uv-plane centre) then spread their atomics over
 // kReplicas addresses instead of one, and the bucket's rows still end up contiguous after
 // the scan.  (Blocks of consecutive rows, not single rows: a bucket's records keep their
@@ -269,19 +269,28 @@ constexpr int kLogReplicas = 6;
 // table; one global atomic per distinct key of the block, and each row's rank is that atomic's
 // return plus its order in the table slot (one atomic per row serialises the lanes that hit a
 // hot bucket; a per-wave leader loop was slower on many small channels).
-// rows per k_key block: the hash aggregation spans the block, and consecutive rows (one time
-// step's baselines) repeat keys more often over a longer span (C2: 0.77 distinct keys per row
-// over 256 rows, 0.51 over 1024)
+// A block of kKeyThreads threads takes kKeyRowsPerThread rows each: consecutive rows (one time
+// step's baselines, then the next steps') repeat keys more often over a longer span (C2: 0.77
+// distinct keys per row over 256 rows, 0.51 over 1024), so a longer block takes fewer global
+// atomics, and fewer of them meet on one counter.  4096-row blocks (about two time steps of the
+// 60-station array) against 1024: key stage 2.26 -> 0.92 ms on the 8192^2 LOFAR-shaped image
+// (where almost every row of one time step has a bucket of its own), 0.19 -> 0.10 ms on C2.
 #ifndef WSIMG_KEY_THREADS
 #define WSIMG_KEY_THREADS 1024
 #endif
+#ifndef WSIMG_KEY_ROWS_PER_THREAD
+#define WSIMG_KEY_ROWS_PER_THREAD 4
+#endif
 constexpr int kKeyThreads = WSIMG_KEY_THREADS;
+constexpr int kKeyRowsPerThread = WSIMG_KEY_ROWS_PER_THREAD;
+constexpr int kKeyRows = kKeyThreads * kKeyRowsPerThread;
 static_assert(kKeyThreads == 256 || kKeyThreads == 512 || kKeyThreads == 1024, "k_key block size");
+static_assert(kKeyRowsPerThread == 1 || kKeyRowsPerThread == 2 || kKeyRowsPerThread == 4, "k_key rows per thread");
 
 // Replica of the bucket counters that row i of a channel counts in: its k_key block's index
 // mod kReplicas (k_key and k_scatter must agree on it).
 __device__ __forceinline__ uint32_t row_replica(int64_t i) {
-    return (uint32_t)((i / kKeyThreads) & (kReplicas - 1));
+    return (uint32_t)((i / kKeyRows) & (kReplicas - 1));
 }
 
 template <typename WT>
@@ -289,51 +298,68 @@ __global__ void __launch_bounds__(kKeyThreads)
 k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom g,
       const Scalars* __restrict__ sc, uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
       uint32_t* __restrict__ counts) {
+    constexpr int KR = kKeyRowsPerThread;
     const int c = blockIdx.y;
     const int64_t r0 = ch.row_off[c], r1 = ch.row_off[c + 1];
-    if ((int64_t)blockIdx.x * blockDim.x >= r1 - r0) return;       // whole block past the channel
-    const int64_t m = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = m < r1;
-    uint32_t kk = 0xFFFFFFFFu;
-    if (in) {
-        const double wt = (double)wts[m];
-        RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support, g.fold_w);
-        if (rg.keep) {
-            const int k = g.wsup ? w_taps(rg.w, sc[c].w_lo, sc[c].dw, g.nw, g.whalf).k0
-                                 : plane_index(rg.w, sc[c].w_lo, sc[c].dw, g.nw);
-            const int p0 = (int)rg.cy - g.half;
-            kk = (uint32_t)(c * g.nb1 + k * g.S + (p0 >> g.log2H));
+    const int64_t b0 = r0 + (int64_t)blockIdx.x * kKeyRows;
+    if (b0 >= r1) return;                                           // whole block past the channel
+    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+    uint32_t kk[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        const int64_t m = b0 + j * kKeyThreads + threadIdx.x;
+        kk[j] = kEmpty;
+        if (m < r1) {
+            const double wt = (double)wts[m];
+            RowGeom rg = row_geometry(uvw, m, ch.freq[c], g.du, g.half_n, wt, g.n, g.support, g.fold_w);
+            if (rg.keep) {
+                const int k = g.wsup ? w_taps(rg.w, sc[c].w_lo, sc[c].dw, g.nw, g.whalf).k0
+                                     : plane_index(rg.w, sc[c].w_lo, sc[c].dw, g.nw);
+                const int p0 = (int)rg.cy - g.half;
+                kk[j] = (uint32_t)(c * g.nb1 + k * g.S + (p0 >> g.log2H));
+            }
         }
     }
-    const uint32_t rep = row_replica((int64_t)blockIdx.x * kKeyThreads);
+    const uint32_t rep = row_replica((int64_t)blockIdx.x * kKeyRows);
     // block-wide aggregation through an LDS hash table (open addressing, 2x the block's
-    // rows, so a free slot always exists): each distinct key of the block takes one atomic
-    constexpr int kSlots = 2 * kKeyThreads;
-    constexpr int kSlotBits = kKeyThreads == 256 ? 9 : (kKeyThreads == 512 ? 10 : 11);
-    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-    __shared__ uint32_t hkey[kSlots], hcnt[kSlots], hbase[kSlots];
+    // rows, so a free slot always exists): each distinct key of the block takes one atomic,
+    // whose return replaces the slot's count
+    constexpr int kSlots = 2 * kKeyRows;
+    constexpr int kSlotBits = kSlots == 512 ? 9 : kSlots == 1024 ? 10 : kSlots == 2048 ? 11
+                            : kSlots == 4096 ? 12 : 13;
+    static_assert((1 << kSlotBits) == kSlots, "hash table size");
+    __shared__ uint32_t hkey[kSlots], hcnt[kSlots];
     for (int i = threadIdx.x; i < kSlots; i += blockDim.x) { hkey[i] = kEmpty; hcnt[i] = 0u; }
     __syncthreads();
-    uint32_t slot = 0, local = 0;
-    if (kk != kEmpty) {
-        slot = (kk * 2654435761u) >> (32 - kSlotBits);   // multiplicative hash
-        while (true) {
-            const uint32_t prev = atomicCAS(&hkey[slot], kEmpty, kk);
-            if (prev == kEmpty || prev == kk) break;
-            slot = (slot + 1) & (kSlots - 1);
+    uint32_t slot[KR], local[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        slot[j] = 0;
+        local[j] = 0;
+        if (kk[j] != kEmpty) {
+            uint32_t sl = (kk[j] * 2654435761u) >> (32 - kSlotBits);   // multiplicative hash
+            while (true) {
+                const uint32_t prev = atomicCAS(&hkey[sl], kEmpty, kk[j]);
+                if (prev == kEmpty || prev == kk[j]) break;
+                sl = (sl + 1) & (kSlots - 1);
+            }
+            slot[j] = sl;
+            local[j] = atomicAdd(&hcnt[sl], 1u);
         }
-        local = atomicAdd(&hcnt[slot], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kSlots; i += blockDim.x) {
         const uint32_t key_i = hkey[i];
-        if (key_i != kEmpty) hbase[i] = atomicAdd(&counts[((size_t)key_i << kLogReplicas) + rep], hcnt[i]);
+        if (key_i != kEmpty) hcnt[i] = atomicAdd(&counts[((size_t)key_i << kLogReplicas) + rep], hcnt[i]);
     }
     __syncthreads();
-    const uint32_t rr = kk != kEmpty ? hbase[slot] + local : 0u;
-    if (in) {
-        key[m] = kk;
-        rank[m] = rr;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        const int64_t m = b0 + j * kKeyThreads + threadIdx.x;
+        if (m < r1) {
+            key[m] = kk[j];
+            rank[m] = kk[j] != kEmpty ? hcnt[slot[j]] + local[j] : 0u;
+        }
     }
 }
 
@@ -503,8 +529,9 @@ __device__ __forceinline__ uint32_t frac_code(double f) {
 
 // vis may be null (prediction: the records carry positions only, W*V = 0); rec_idx, when not
 // null, receives each record's input row.
-// rows per k_scatter block: blocks of 1024 (like k_key's) write the records of a row block's
-// buckets from one work-group (C2 scatter 0.20 -> 0.18 ms, 64 channels of 1024^2 0.99 -> 0.80 ms)
+// rows per k_scatter block: blocks of 1024 rows (a quarter of a k_key block, whose replica they
+// share) write the records of their buckets from one work-group (C2 scatter 0.20 -> 0.18 ms
+// against 256-row blocks, 64 channels of 1024^2 0.99 -> 0.80 ms)
 #ifndef WSIMG_SCATTER_THREADS
 #define WSIMG_SCATTER_THREADS 1024
 #endif

@@ -514,7 +514,7 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     if (auto r = st.after(1)) return r;
 
     if (M > 0) {
-        hipLaunchKernelGGL((k_key<R>), dim3(blocks_for(M, kKeyThreads), nch), dim3(kKeyThreads), 0, s, ch, uvw, (const R*)wts,
+        hipLaunchKernelGGL((k_key<R>), dim3(blocks_for(M, kKeyRows), nch), dim3(kKeyThreads), 0, s, ch, uvw, (const R*)wts,
                            g, pl->scalars, pl->key, pl->rank, pl->counts);
         WS_LAUNCH_CHECK("key");
     }

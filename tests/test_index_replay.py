@@ -32,7 +32,7 @@ import pytest
 
 C_LIGHT = 299_792_458.0
 REPLICAS = 64                 # bucket counter replicas
-KEY_ROWS = 1024               # rows per key / scatter block (replica = block mod 64)
+KEY_ROWS = 4096               # rows per key block (replica = block mod 64; the scatter follows it)
 ORIGIN_BINS = 8192            # LDS histogram of the origin sort
 HEAVY = 4096                  # record visits above which a strip goes to the front of the list
 MIN_PART = 4096
