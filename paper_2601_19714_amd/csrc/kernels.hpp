@@ -251,7 +251,14 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
         r.n_occ = 0;
         r.n_planes = 0;
         sc[c] = r;
-        if (c == 0) *wl = WorkList{};
+        if (c == 0) {       // the counters only (a whole-struct store takes 25 us from one thread)
+            wl->n_heavy = 0u;
+            wl->n_light = 0u;
+            wl->n_split = 0u;
+            wl->next = 0u;
+#pragma unroll
+            for (int x = 0; x < 8; ++x) wl->xnext[x].n = 0u;
+        }
     }
 }
 
@@ -666,6 +673,9 @@ __device__ __forceinline__ uint32_t raw_origin(const RawRec<R>& x, int log2H) {
 // a run of them in registers before adding it to the strip once: on 8 s integrations a
 // baseline stays in one grid cell for several steps, and dense buckets hold tens of records
 // per origin.
+#ifndef WSIMG_SORT_UNROLL
+#define WSIMG_SORT_UNROLL 8
+#endif
 constexpr int kOriginBins = 8192;
 constexpr int kSortThreads = 512;
 
@@ -723,7 +733,19 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
 #pragma unroll
     for (int i = 0; i < PER; ++i) hist[i * kSortThreads + t] = 0u;
     __syncthreads();
-    for (uint32_t r = beg + t; r < end; r += kSortThreads)
+    // U records per thread in flight before their atomics (a bucket of the uv centre holds up
+    // to 7e5 records, all walked by this one work-group)
+    constexpr int U = WSIMG_SORT_UNROLL;
+    constexpr uint32_t US = (uint32_t)U * kSortThreads;
+    uint32_t r = beg + t;
+    for (; r + (U - 1) * kSortThreads < end; r += US) {
+        uint32_t o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) o[u] = raw_origin<R>(fetch_record<R>(rec_cell, rec, r + u * kSortThreads), g.log2H);
+#pragma unroll
+        for (int u = 0; u < U; ++u) atomicAdd(&hist[o[u]], 1u);
+    }
+    for (; r < end; r += kSortThreads)
         atomicAdd(&hist[raw_origin<R>(fetch_record<R>(rec_cell, rec, r), g.log2H)], 1u);
     __syncthreads();
     // exclusive scan of the bins: thread t owns bins [t * PER, (t + 1) * PER); the thread sums
@@ -745,7 +767,23 @@ k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __re
 #pragma unroll
     for (int i = 0; i < PER; ++i) { hist[t * PER + i] = run; run += v[i]; }
     __syncthreads();
-    for (uint32_t r = beg + t; r < end; r += kSortThreads) {
+    r = beg + t;
+    for (; r + (U - 1) * kSortThreads < end; r += US) {
+        RawRec<R> x[U];
+        R xw[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            x[u] = fetch_record<R>(rec_cell, rec, r + u * kSortThreads);
+            xw[u] = rec_w ? rec_w[r + u * kSortThreads] : (R)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t to = beg + atomicAdd(&hist[raw_origin<R>(x[u], g.log2H)], 1u);
+            store_record<R>(rec_cell2, rec2, to, x[u]);
+            if (rec_w) rec_w2[to] = xw[u];
+        }
+    }
+    for (; r < end; r += kSortThreads) {
         const RawRec<R> x = fetch_record<R>(rec_cell, rec, r);
         const uint32_t to = beg + atomicAdd(&hist[raw_origin<R>(x, g.log2H)], 1u);
         store_record<R>(rec_cell2, rec2, to, x);

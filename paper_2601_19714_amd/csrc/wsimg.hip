@@ -263,13 +263,14 @@ wsimg_status set_lds_limits(wsimg_plan* pl) {
         if (e_ != hipSuccess) return fail(WSIMG_E_HIP, std::string("launch ") + what + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// The records are put in origin order inside each bucket (k_origin_sort) for the float plan
-// only: in float64 the sort (36-byte records) costs more than the longer runs save (C2 float64
-// 5.79 -> 5.44 ms without it; float32 3.03 -> 3.00 ms with it), and its gridding reads the
-// records in bucket order.
+// The records are put in origin order inside each bucket (k_origin_sort) for the float plan,
+// and for the float64 plan at 8192^2 only: below it the float64 sort (36-byte records) costs
+// more than the longer runs save (4096^2 float64 5.28 ms without it, 5.42 ms with it), at
+// 8192^2, where a record is walked once per grid row of its taps, it pays (90.7 -> 86.2 ms:
+// gridding 47.5 -> 40.0 ms for a 3.1 ms sort).  Unsorted plans grid in bucket order.
 // (Without the origin sort the 8192^2 float gridding took 34.4 ms against 17.6 ms.)
-template <typename R> bool origin_sorted(int) { return sizeof(R) == 4; }
-bool origin_sorted_plan(bool f32, int) { return f32; }
+template <typename R> bool origin_sorted(int log2n) { return sizeof(R) == 4 || log2n == 13; }
+bool origin_sorted_plan(bool f32, int log2n) { return f32 || log2n == 13; }
 
 // WMAX: the support class the gridding registers are sized for (W <= 7, else W <= 15).
 template <typename R, int LOG2N, int WMAX>
