@@ -40,7 +40,8 @@ CANDIDATES = {
     "stack_r16": ["-DWSIMG_F32_LR2_N{L}=4"],
     "strip_rows2": ["-DWSIMG_STRIP_ROWS_N{L}=2"],
     "strip_rows4": ["-DWSIMG_STRIP_ROWS_N{L}=4"],
-    "chunk32": ["-DWSIMG_GRID_CHUNK_MAX=32"],
+    "chunk32": ["-DWSIMG_F32_GRID_CHUNK_MAX=32"],
+    "chunk128": ["-DWSIMG_F32_GRID_CHUNK_MAX=128"],
     "walk128": ["-DWSIMG_WALK_VGPRS=128"],
 }
 # the image sizes (log2 n) a per-shape candidate's macro applies to

@@ -38,7 +38,7 @@ HEAVY = 4096                  # record visits above which a strip goes to the fr
 MIN_PART = 4096
 MAX_PARTS = 32
 MAX_SPLIT = 512
-CHUNK_MAX = 16                # records per gridding work item
+CHUNK_MAX = {"f32": 64, "f64": 16}   # records per gridding work item, by precision
 MAX_LDS = 160 * 1024
 CUS = 256                     # MI355X compute units (the persistent grid's size)
 
@@ -231,7 +231,7 @@ def replay(uvw, wt, freq, prm, info, prec):
             nv = pe - pb
             if nv <= 0:
                 continue
-            chunk = min(max(-(-(nv * NG) // NT), 1), CHUNK_MAX)
+            chunk = min(max(-(-(nv * NG) // NT), 1), CHUNK_MAX[prec])
             items = -(-nv // chunk)
             last_r = pb + (items - 1) * chunk
             re = min(last_r + chunk, pe)
@@ -283,7 +283,7 @@ def pipelined_walk_overread(vbeg, vend, NT):
         nv = int(b1 - b0)
         if nv <= 0:
             continue
-        chunk = min(max(nv // NT, 1), CHUNK_MAX)
+        chunk = min(max(nv // NT, 1), 16)       # that walk's chunks: at most 16 records
         items = -(-nv // chunk)
         re = min(int(b0) + items * chunk, int(b1))
         mx = max(mx, re)          # one past the last record of the last chunk
