@@ -25,10 +25,29 @@ The work-group shapes are mirrored here from the kernels' compile-time rules and
 what the library itself reports, so a drift between the two fails the test.
 """
 
+import json
 import math
+import os
 
 import numpy as np
 import pytest
+
+
+def _tuned_macros():
+    """The -DNAME=VALUE flags of the autotuner's record, which the library build adds."""
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2601_19714_amd", "tuned.json")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            for f in json.load(fh).get("flags", []):
+                if f.startswith("-D") and "=" in f:
+                    k, v = f[2:].split("=", 1)
+                    out[k] = int(v)
+    return out
+
+
+TUNED = _tuned_macros()
 
 C_LIGHT = 299_792_458.0
 REPLICAS = 64                 # bucket counter replicas
@@ -38,7 +57,8 @@ HEAVY = 4096                  # record visits above which a strip goes to the fr
 MIN_PART = 4096
 MAX_PARTS = 32
 MAX_SPLIT = 512
-CHUNK_MAX = {"f32": 64, "f64": 16}   # records per gridding work item, by precision
+CHUNK_MAX = {"f32": TUNED.get("WSIMG_F32_GRID_CHUNK_MAX", 64),
+             "f64": TUNED.get("WSIMG_F64_GRID_CHUNK_MAX", 16)}   # records per gridding work item
 MAX_LDS = 160 * 1024
 CUS = 256                     # MI355X compute units (the persistent grid's size)
 
@@ -60,9 +80,10 @@ def shape(prec, log2n):
     f32 = prec == "f32"
     N = 1 << log2n
     lr1 = min(4, log2n - 1)
-    lr2 = min((4 if log2n == 12 else 3) if f32 else 3, log2n - 1)
+    lr2_f32 = TUNED.get(f"WSIMG_F32_LR2_N{log2n}", 4 if log2n == 12 else 3)
+    lr2 = min(lr2_f32 if f32 else 3, log2n - 1)
     cap1 = 8192 if log2n >= 12 else 4096
-    hs = 2                                                    # rows per strip below 4096^2 (0: by cells)
+    hs = TUNED.get(f"WSIMG_STRIP_ROWS_N{log2n}", 2)           # rows per strip below 4096^2 (0: by cells)
     h0 = hs if (log2n < 12 and hs > 0) else min(4, max(1, cap1 // N))
     H = min(h0, N // 2)
     nt1 = max(64, H * N >> lr1)
@@ -86,7 +107,7 @@ def shape(prec, log2n):
 def walk_rows(W):
     """Register rows per gridding walk for the support class (W <= 7: 7 taps, W = 9: 9, else 15)."""
     wmax = 7 if W <= 7 else (9 if W == 9 else 15)
-    fit = 64 // (wmax * 4)
+    fit = TUNED.get("WSIMG_WALK_VGPRS", 64) // (wmax * 4)
     return 8 if fit >= 8 else 4 if fit >= 4 else 2 if fit >= 2 else 1
 
 
