@@ -72,6 +72,7 @@ struct WorkList {
     unsigned int n_heavy, n_light, n_split, pad0[29];
     unsigned int next, pad1[31];
     struct { unsigned int n, pad[31]; } xnext[8];   // per-XCD counters over the light entries
+    unsigned int n_big, pad2[31];                    // buckets in the big-bucket list (k_origin_sort)
 };
 
 // Heavy strips are split.  With `share` the record visits of the call over the gridding
@@ -258,6 +259,7 @@ k_finalize(int nparts, const Partial* __restrict__ part, Geom g, Chan ch, Scalar
             wl->next = 0u;
 #pragma unroll
             for (int x = 0; x < 8; ++x) wl->xnext[x].n = 0u;
+            wl->n_big = 0u;
         }
     }
 }
@@ -450,16 +452,24 @@ k_scan_down(int64_t total, const uint32_t* __restrict__ counts, const uint32_t* 
 // kHeavyStrip record visits from the front (list[0..n_heavy)), the rest from the back
 // (list[nb - n_light .. nb)), so the long ones start first.  Counts go to the scalars.
 constexpr uint32_t kHeavyStrip = 4096;
+// Buckets of more records than this are origin-sorted first (their list is built here): the
+// uv-centre buckets of an 8192^2 image hold up to 7e5 records, each walked by one work-group,
+// and started in bucket order they would begin half-way through the sort and end after it.
+constexpr uint32_t kBigBucket = 16384;
 
 __global__ void __launch_bounds__(256)
 k_occupancy(int nch, const uint32_t* __restrict__ offsets, Geom g, uint8_t* __restrict__ occ,
             uint8_t* __restrict__ plane_occ, uint32_t* __restrict__ list, uint32_t* __restrict__ list_aux,
-            uint32_t list_cap, uint32_t share, Scalars* __restrict__ sc, WorkList* __restrict__ wl) {
+            uint32_t list_cap, uint32_t share, Scalars* __restrict__ sc, WorkList* __restrict__ wl,
+            uint32_t* __restrict__ big) {
     const int total = nch * g.nb1;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t o = 0, po = 0, visits = 0;
     int c = 0;
     if (b < total) {
+        // the origin sort's big buckets (bucket b itself; at most rows / kBigBucket of them)
+        if (big && offsets[(size_t)(b + 1) << kLogReplicas] - offsets[(size_t)b << kLogReplicas] > kBigBucket)
+            big[atomicAdd(&wl->n_big, 1u)] = (uint32_t)b;
         c = b / g.nb1;
         const int bb = b - c * g.nb1;
         const int k = bb / g.S, sidx = bb - k * g.S;
@@ -679,17 +689,27 @@ __device__ __forceinline__ uint32_t raw_origin(const RawRec<R>& x, int log2H) {
 constexpr int kOriginBins = 8192;
 constexpr int kSortThreads = 512;
 
-// Work-group (x, c) = bucket x of channel c.
+// One work-group per bucket (the big ones first).
 template <typename R>
 __global__ void __launch_bounds__(kSortThreads)
 k_origin_sort(Geom g, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ rec_cell,
               const void* __restrict__ rec, uint32_t* __restrict__ rec_cell2, void* __restrict__ rec2,
-              const R* __restrict__ rec_w, R* __restrict__ rec_w2) {
+              const R* __restrict__ rec_w, R* __restrict__ rec_w2, const uint32_t* __restrict__ big,
+              uint32_t big_cap, const WorkList* __restrict__ wl) {
     __shared__ uint32_t hist[kOriginBins];
     __shared__ uint32_t part[kSortThreads / 64];
     constexpr int PER = kOriginBins / kSortThreads;
-    const size_t b = (size_t)blockIdx.y * g.nb1 + blockIdx.x;
+    // blocks x < big_cap take the listed big buckets (dispatched first); the others take bucket
+    // x - big_cap (channel * nb1 + plane * S + strip) unless it is big
+    size_t b;
+    if (blockIdx.x < big_cap) {
+        if (blockIdx.x >= wl->n_big) return;
+        b = big[blockIdx.x];
+    } else {
+        b = (size_t)blockIdx.x - big_cap;
+    }
     const uint32_t beg = offsets[b << kLogReplicas], end = offsets[(b + 1) << kLogReplicas];
+    if (blockIdx.x >= big_cap && end - beg > kBigBucket) return;
     const int t = threadIdx.x;
     if (end - beg <= 1) {
         if (end - beg == 1 && t == 0) {

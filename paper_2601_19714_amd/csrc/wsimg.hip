@@ -76,6 +76,8 @@ struct wsimg_plan {
     uint32_t* list = nullptr;      // work list of occupied strips (heavy ones split into parts)
     uint32_t* list_aux = nullptr;  // each entry's part word
     uint32_t list_cap = 0;
+    uint32_t* big = nullptr;       // the origin sort's big buckets (listed by k_occupancy)
+    uint32_t big_cap = 0;          // rows / kBigBucket + 1 when the plan origin-sorts, else 0
     double2* split_acc = nullptr;  // float64 sums of split strips (zero between calls)
     uint32_t* split_done = nullptr;
     int persist_blocks = 256;      // work-groups of the persistent gridding kernel
@@ -534,9 +536,11 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     // a strip gridded from several planes' rows (the w-kernel) is not split into parts
     const int64_t share = (pl->no_split || g.wsup) ? int64_t(0x3FFFFFFF)
                                        : std::max<int64_t>(kMinPart, visits / std::max(1, pl->persist_blocks));
+    const bool osort = M > 0 && !predict && origin_sorted<R>(g.log2n) && pl->big_cap > 0;
     hipLaunchKernelGGL(k_occupancy, dim3(blocks_for(nbk, 256)), dim3(256), 0, s, nch, pl->offsets, g,
                        pl->occ, pl->plane_occ, pl->list, pl->list_aux, pl->list_cap,
-                       (uint32_t)std::min<int64_t>(share, 0x3FFFFFFF), pl->scalars, pl->worklist);
+                       (uint32_t)std::min<int64_t>(share, 0x3FFFFFFF), pl->scalars, pl->worklist,
+                       osort ? pl->big : nullptr);
     WS_LAUNCH_CHECK("occupancy");
     if (auto r = st.after(3)) return r;
 
@@ -549,10 +553,12 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     }
     if (auto r = st.after(4)) return r;
 
-    if (M > 0 && !predict && origin_sorted<R>(g.log2n)) {
-        hipLaunchKernelGGL((k_origin_sort<R>), dim3((unsigned)pl->nb, nch), dim3(kSortThreads), 0, s, g,
+    if (osort) {
+        // the first big_cap blocks take the listed big buckets, the rest every bucket of every channel
+        hipLaunchKernelGGL((k_origin_sort<R>), dim3((unsigned)(pl->big_cap + nbk)), dim3(kSortThreads), 0, s, g,
                            pl->offsets, pl->rec_cell, (const void*)pl->rec, pl->rec_cell2, pl->rec2,
-                           g.wsup ? (const R*)pl->rec_w : nullptr, g.wsup ? (R*)pl->rec_w2 : nullptr);
+                           g.wsup ? (const R*)pl->rec_w : nullptr, g.wsup ? (R*)pl->rec_w2 : nullptr,
+                           (const uint32_t*)pl->big, pl->big_cap, (const WorkList*)pl->worklist);
         WS_LAUNCH_CHECK("origin_sort");
     }
     if (auto r = st.after(5)) return r;
@@ -694,6 +700,9 @@ wsimg_status plan_geometry(wsimg_plan* pl, const wsimg_params* p, int64_t max_vi
     if (pl->nb * max_channels > kMaxBucketsTotal)
         return fail(WSIMG_E_UNSUPPORTED, "max_channels x n_wplanes x strips exceeds 2^25 sort buckets");
     pl->list_cap = (uint32_t)((size_t)pl->nb * max_channels + (size_t)kMaxSplit * kMaxParts);
+    // a big bucket holds more than kBigBucket of the call's rows, so there are fewer than this
+    pl->big_cap = origin_sorted_plan(f32, g.log2n)
+                      ? (uint32_t)(((size_t)std::max<int64_t>(max_vis, 1) + kRowSlack) / kBigBucket + 1) : 0u;
     return WSIMG_OK;
 }
 
@@ -724,6 +733,7 @@ wsimg_status for_each_allocation(wsimg_plan* pl, F&& f) {
     WS_ALLOC(occ, nbt, "occupancy");
     WS_ALLOC(list, sizeof(uint32_t) * pl->list_cap, "strip work list");
     WS_ALLOC(list_aux, sizeof(uint32_t) * pl->list_cap, "strip work list parts");
+    WS_ALLOC(big, sizeof(uint32_t) * std::max<uint32_t>(pl->big_cap, 1), "big-bucket list");
     WS_ALLOC(split_acc, pl->no_split ? 256 : (size_t)kMaxSplit * pl->lds1, "split strip sums");
     WS_ALLOC(split_done, pl->no_split ? 256 : sizeof(uint32_t) * kMaxSplit, "split strip counters");
     WS_ALLOC(plane_occ, (size_t)g.nw * mc, "plane occupancy");

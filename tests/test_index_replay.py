@@ -53,6 +53,7 @@ C_LIGHT = 299_792_458.0
 REPLICAS = 64                 # bucket counter replicas
 KEY_ROWS = 4096               # rows per key block (replica = block mod 64; the scatter follows it)
 ORIGIN_BINS = 8192            # LDS histogram of the origin sort
+BIG_BUCKET = 16384            # buckets above this many records are origin-sorted first, from a list
 HEAVY = 4096                  # record visits above which a strip goes to the front of the list
 MIN_PART = 4096
 MAX_PARTS = 32
@@ -200,6 +201,9 @@ def replay(uvw, wt, freq, prm, info, prec):
     by_pos[pos] = np.arange(n_kept)
     bucket_of_rec = kk[by_pos]
     bstart = offsets[np.arange(nb + 1) * REPLICAS]            # bucket b = [bstart[b], bstart[b+1])
+    # k_occupancy's big-bucket list fits its capacity (row capacity / BIG_BUCKET + 1 entries)
+    n_big = int((np.diff(bstart) > BIG_BUCKET).sum())
+    assert n_big < info["row_capacity"] // BIG_BUCKET + 1
     # decoding p0 from the bucket's strip and the stored row-in-strip gives the row's own p0
     strip_of_rec = bucket_of_rec % S
     assert np.array_equal((strip_of_rec << log2H) + pr[by_pos], p0[by_pos])
