@@ -279,11 +279,11 @@ constexpr int kLogReplicas = 6;
 // return plus its order in the table slot (one atomic per row serialises the lanes that hit a
 // hot bucket; a per-wave leader loop was slower on many small channels).
 // A block of kKeyThreads threads takes kKeyRowsPerThread rows each: consecutive rows (one time
-// step's baselines, then the next steps') repeat keys more often over a longer span (C2: 0.77
-// distinct keys per row over 256 rows, 0.51 over 1024), so a longer block takes fewer global
+// step's baselines, then the next steps') repeat keys more often over a longer span (the 4096^2
+// MeerKAT-shaped set: 0.77 distinct keys per row over 256 rows, 0.51 over 1024), so a longer block takes fewer global
 // atomics, and fewer of them meet on one counter.  4096-row blocks (about two time steps of the
 // 60-station array) against 1024: key stage 2.26 -> 0.92 ms on the 8192^2 LOFAR-shaped image
-// (where almost every row of one time step has a bucket of its own), 0.19 -> 0.10 ms on C2.
+// (where almost every row of one time step has a bucket of its own), 0.19 -> 0.10 ms at 4096^2.
 #ifndef WSIMG_KEY_THREADS
 #define WSIMG_KEY_THREADS 1024
 #endif
@@ -420,28 +420,48 @@ k_scan_top(int ntiles, uint32_t* __restrict__ tile_sums) {
 __global__ void __launch_bounds__(256)
 k_scan_down(int64_t total, const uint32_t* __restrict__ counts, const uint32_t* __restrict__ tile_offs,
             uint32_t* __restrict__ offsets) {
-    __shared__ uint32_t part[256];
+    __shared__ uint32_t part[4];
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * 16;
+    // a thread's 16 entries start 64-byte aligned: whole ones move as four 16-byte accesses
+    const bool whole = base + 16 <= total;
     uint32_t v[16], s = 0;
+    if (whole) {
+        const uint4* c4 = reinterpret_cast<const uint4*>(counts + base);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        v[i] = base + i < total ? counts[base + i] : 0u;
-        s += v[i];
+        for (int q = 0; q < 4; ++q) {
+            const uint4 x = c4[q];
+            v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = base + i < total ? counts[base + i] : 0u;
     }
-    part[t] = s;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += v[i];
+    // exclusive scan of the 256 thread sums: within each wave by shuffles, then the wave totals
+    const int lane = t & 63, wave = t >> 6;
+    uint32_t inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) part[wave] = inc;
     __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        uint32_t x = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
-    }
-    uint32_t run = tile_offs[blockIdx.x] + (t > 0 ? part[t - 1] : 0u);
+    uint32_t run = tile_offs[blockIdx.x] + (inc - s);
+    for (int w = 0; w < wave; ++w) run += part[w];
+    uint32_t o[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        if (base + i < total) offsets[base + i] = run;
-        run += v[i];
+    for (int i = 0; i < 16; ++i) { o[i] = run; run += v[i]; }
+    if (whole) {
+        uint4* o4 = reinterpret_cast<uint4*>(offsets + base);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o4[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (base + i < total) offsets[base + i] = o[i];
     }
     if (base + 16 >= total && base < total) offsets[total] = run;   // the thread holding the last entry
 }
@@ -547,7 +567,7 @@ __device__ __forceinline__ uint32_t frac_code(double f) {
 // vis may be null (prediction: the records carry positions only, W*V = 0); rec_idx, when not
 // null, receives each record's input row.
 // rows per k_scatter block: blocks of 1024 rows (a quarter of a k_key block, whose replica they
-// share) write the records of their buckets from one work-group (C2 scatter 0.20 -> 0.18 ms
+// share) write the records of their buckets from one work-group (4096^2: 0.20 -> 0.18 ms
 // against 256-row blocks, 64 channels of 1024^2 0.99 -> 0.80 ms)
 #ifndef WSIMG_SCATTER_THREADS
 #define WSIMG_SCATTER_THREADS 1024
