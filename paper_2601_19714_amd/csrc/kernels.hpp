@@ -281,20 +281,32 @@ constexpr int kLogReplicas = 6;
 // A block of kKeyThreads threads takes kKeyRowsPerThread rows each: consecutive rows (one time
 // step's baselines, then the next steps') repeat keys more often over a longer span (the 4096^2
 // MeerKAT-shaped set: 0.77 distinct keys per row over 256 rows, 0.51 over 1024), so a longer block takes fewer global
-// atomics, and fewer of them meet on one counter.  4096-row blocks (about two time steps of the
-// 60-station array) against 1024: key stage 2.26 -> 0.92 ms on the 8192^2 LOFAR-shaped image
-// (where almost every row of one time step has a bucket of its own), 0.19 -> 0.10 ms at 4096^2.
+// atomics, and fewer of them meet on one counter.  On the 8192^2 LOFAR-shaped image (where
+// almost every row of one time step has a bucket of its own) the key stage took 2.26 ms with
+// 1024-row blocks, 0.92 ms with 4096 (about two time steps of the 60-station array) and 0.59 ms
+// with 8192; at 4096^2 0.19, 0.10 and 0.076 ms.
 #ifndef WSIMG_KEY_THREADS
 #define WSIMG_KEY_THREADS 1024
 #endif
 #ifndef WSIMG_KEY_ROWS_PER_THREAD
-#define WSIMG_KEY_ROWS_PER_THREAD 4
+#define WSIMG_KEY_ROWS_PER_THREAD 8
 #endif
 constexpr int kKeyThreads = WSIMG_KEY_THREADS;
 constexpr int kKeyRowsPerThread = WSIMG_KEY_ROWS_PER_THREAD;
 constexpr int kKeyRows = kKeyThreads * kKeyRowsPerThread;
 static_assert(kKeyThreads == 256 || kKeyThreads == 512 || kKeyThreads == 1024, "k_key block size");
-static_assert(kKeyRowsPerThread == 1 || kKeyRowsPerThread == 2 || kKeyRowsPerThread == 4, "k_key rows per thread");
+static_assert(kKeyRowsPerThread >= 1 && kKeyRowsPerThread <= 8, "k_key rows per thread");
+// slots of the block's hash table (more than the block's rows, so a free slot always exists);
+// two 4-byte words each, in dynamic LDS.  1.25 slots per row keep the table at 80 KB for 8192
+// rows, two blocks per CU (the distinct keys of a block are about a quarter of its rows, so
+// probes stay short); 2 per row (128 KB, one block per CU) made the 8192^2 key stage 0.87 ms
+// against 0.59 ms.
+#ifndef WSIMG_KEY_SLOTS
+#define WSIMG_KEY_SLOTS (kKeyRows + kKeyRows / 4)
+#endif
+constexpr int kKeySlots = WSIMG_KEY_SLOTS;
+static_assert(kKeySlots > kKeyRows, "k_key hash table size");
+constexpr size_t kKeyLdsBytes = (size_t)kKeySlots * 8;
 
 // Replica of the bucket counters that row i of a channel counts in: its k_key block's index
 // mod kReplicas (k_key and k_scatter must agree on it).
@@ -330,14 +342,13 @@ k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom 
         }
     }
     const uint32_t rep = row_replica((int64_t)blockIdx.x * kKeyRows);
-    // block-wide aggregation through an LDS hash table (open addressing, 2x the block's
-    // rows, so a free slot always exists): each distinct key of the block takes one atomic,
-    // whose return replaces the slot's count
-    constexpr int kSlots = 2 * kKeyRows;
-    constexpr int kSlotBits = kSlots == 512 ? 9 : kSlots == 1024 ? 10 : kSlots == 2048 ? 11
-                            : kSlots == 4096 ? 12 : 13;
-    static_assert((1 << kSlotBits) == kSlots, "hash table size");
-    __shared__ uint32_t hkey[kSlots], hcnt[kSlots];
+    // block-wide aggregation through an LDS hash table (open addressing with more slots than
+    // the block's rows, so a free slot always exists): each distinct key of the block takes one
+    // atomic, whose return replaces the slot's count
+    constexpr int kSlots = kKeySlots;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint32_t* hkey = reinterpret_cast<uint32_t*>(smem_raw);
+    uint32_t* hcnt = hkey + kSlots;
     for (int i = threadIdx.x; i < kSlots; i += blockDim.x) { hkey[i] = kEmpty; hcnt[i] = 0u; }
     __syncthreads();
     uint32_t slot[KR], local[KR];
@@ -346,11 +357,12 @@ k_key(Chan ch, const double* __restrict__ uvw, const WT* __restrict__ wts, Geom 
         slot[j] = 0;
         local[j] = 0;
         if (kk[j] != kEmpty) {
-            uint32_t sl = (kk[j] * 2654435761u) >> (32 - kSlotBits);   // multiplicative hash
+            // multiplicative hash, its high bits scaled to [0, kSlots)
+            uint32_t sl = (uint32_t)(((uint64_t)(kk[j] * 2654435761u) * (uint32_t)kSlots) >> 32);
             while (true) {
                 const uint32_t prev = atomicCAS(&hkey[sl], kEmpty, kk[j]);
                 if (prev == kEmpty || prev == kk[j]) break;
-                sl = (sl + 1) & (kSlots - 1);
+                sl = sl + 1 == (uint32_t)kSlots ? 0u : sl + 1;
             }
             slot[j] = sl;
             local[j] = atomicAdd(&hcnt[sl], 1u);
@@ -566,7 +578,7 @@ __device__ __forceinline__ uint32_t frac_code(double f) {
 
 // vis may be null (prediction: the records carry positions only, W*V = 0); rec_idx, when not
 // null, receives each record's input row.
-// rows per k_scatter block: blocks of 1024 rows (a quarter of a k_key block, whose replica they
+// rows per k_scatter block: blocks of 1024 rows (an eighth of a k_key block, whose replica they
 // share) write the records of their buckets from one work-group (4096^2: 0.20 -> 0.18 ms
 // against 256-row blocks, 64 channels of 1024^2 0.99 -> 0.80 ms)
 #ifndef WSIMG_SCATTER_THREADS

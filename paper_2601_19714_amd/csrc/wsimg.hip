@@ -229,6 +229,8 @@ wsimg_status fill_shape(wsimg_plan* pl) {
 template <typename R, int LOG2N>
 wsimg_status set_lds_limits(wsimg_plan* pl) {
     using SH = Shape<R, LOG2N>;
+    WS_HIP(hipFuncSetAttribute((const void*)k_key<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kKeyLdsBytes));
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, 7>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds1));
     WS_HIP(hipFuncSetAttribute((const void*)k_grid_rows<R, LOG2N, 9>,
@@ -517,7 +519,7 @@ wsimg_status run_sort(wsimg_plan* pl, Stamp& st, const Batch& bt, const double* 
     if (auto r = st.after(1)) return r;
 
     if (M > 0) {
-        hipLaunchKernelGGL((k_key<R>), dim3(blocks_for(M, kKeyRows), nch), dim3(kKeyThreads), 0, s, ch, uvw, (const R*)wts,
+        hipLaunchKernelGGL((k_key<R>), dim3(blocks_for(M, kKeyRows), nch), dim3(kKeyThreads), kKeyLdsBytes, s, ch, uvw, (const R*)wts,
                            g, pl->scalars, pl->key, pl->rank, pl->counts);
         WS_LAUNCH_CHECK("key");
     }

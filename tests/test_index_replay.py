@@ -51,7 +51,7 @@ TUNED = _tuned_macros()
 
 C_LIGHT = 299_792_458.0
 REPLICAS = 64                 # bucket counter replicas
-KEY_ROWS = 4096               # rows per key block (replica = block mod 64; the scatter follows it)
+KEY_ROWS = 8192               # rows per key block (replica = block mod 64; the scatter follows it)
 ORIGIN_BINS = 8192            # LDS histogram of the origin sort
 BIG_BUCKET = 16384            # buckets above this many records are origin-sorted first, from a list
 HEAVY = 4096                  # record visits above which a strip goes to the front of the list
